@@ -1,0 +1,216 @@
+"""Benchmark of the hybrid lattice Boltzmann timestep on one MI355X.
+
+A step is one full timestep of the method: the force + collide-and-stream
+kernel and the m convection-diffusion substeps.  The default workload is the
+D2Q9 spinodal decomposition on a 1024 x 1024 periodic lattice with FP32
+shifted populations (a = -0.1, b = 0.1, kappa = 0.1, tau = 1, Gamma = 1,
+m = 5, the paper's stencil N = 0.3, Q = 2.5), phi ~ U(-0.01, 0.01) from
+seed 0, n = 1, u = 0; the standard stencil (N = 1/2, Q = 1) is timed beside
+it.  Prints one JSON line.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+BASE = dict(a=-0.1, b=0.1, kappa=0.1, tau=1.0, gamma=1.0)
+PAPER_STENCIL = dict(N=0.3, Q=2.5)
+STANDARD_STENCIL = dict(N=0.5, Q=1.0)
+
+WORKLOADS = {
+    # name: (shape, storage, stencil, description)
+    "d2q9_spinodal_1024": ((1024, 1024), "f32", dict(BASE, **PAPER_STENCIL),
+                           "D2Q9 spinodal 1024x1024 periodic, FP32 shifted populations"),
+    "d2q9_spinodal_4096": ((4096, 4096), "f32", dict(BASE, **PAPER_STENCIL),
+                           "D2Q9 spinodal 4096x4096 periodic, FP32 shifted populations"),
+    "d2q9_drop_128_f64": ((128, 128), "f64", dict(BASE, **PAPER_STENCIL),
+                          "D2Q9 drop R=20 128x128 periodic, FP64"),
+    "d3q19_spinodal_256": ((256, 256, 256), "f32", dict(BASE, N=1 / 6, Q=1 / 3),
+                           "D3Q19 spinodal 256^3 periodic, FP32 shifted populations"),
+}
+
+
+def algorithmic_bytes(d: int, q: int, es: int):
+    """Bytes per lattice update that each kernel must move (and the whole
+    step's minimum): the collide-and-stream kernel reads and writes every
+    population once, reads phi and writes u*; a convection-diffusion substep
+    reads phi and u* and writes phi; the whole step at its minimum reads and
+    writes every population and phi once."""
+    lb = (2 * q + 1 + d) * es
+    ch = (2 + d) * es
+    step_min = (2 * q + 2) * es
+    return lb, ch, step_min
+
+
+def make_inputs(name, shape):
+    import numpy as np
+
+    import synth
+
+    if "drop" in name:
+        a, b, kappa = BASE["a"], BASE["b"], BASE["kappa"]
+        return synth.drop(shape, 20, np.sqrt(-a / b), np.sqrt(-2 * kappa / a))
+    return synth.spinodal(shape, seed=0)
+
+
+def run_gpu(name, steps, warmup):
+    import torch
+
+    from paper_0902_3921_amd import hlb
+
+    shape, storage, kw, desc = WORKLOADS[name]
+    phi0 = make_inputs(name, shape)
+    d = len(shape)
+    q = 9 if d == 2 else 19
+    es = 8 if storage == "f64" else 4
+    ns = 1
+    for s in shape:
+        ns *= s
+
+    def timed(params):
+        sim = hlb.Sim(shape, storage, **params)
+        sim.init(phi0)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        stats = sim.reduce(raise_on_error=False)
+        return sim, t1 - t0, stats
+
+    sim, secs, stats = timed(kw)
+    m = sim.m
+    # per-kernel durations from HIP events on the library's stream
+    nprof = max(20, min(200, steps))
+    ms_lb, ms_ch = sim.step_timed(nprof)
+    names = (sim.kernel_name(0), sim.kernel_name(1))
+    sim.close()
+    sim_sc, secs_sc, _ = timed(dict(kw, **STANDARD_STENCIL))
+    sim_sc.close()
+
+    lb_b, ch_b, step_b = algorithmic_bytes(d, q, es)
+    t_lb = ms_lb / nprof * 1e-3            # s per launch
+    t_ch = ms_ch / (nprof * m) * 1e-3      # s per launch
+    per_step = {"lb": t_lb, "ch": t_ch * m}
+    dominant = max(per_step, key=per_step.get)
+    if dominant == "lb":
+        achieved = lb_b * ns / t_lb / 1e9
+        kname, kbytes = names[0], lb_b
+    else:
+        achieved = ch_b * ns / t_ch / 1e9
+        kname, kbytes = names[1], ch_b
+    mlups = ns * steps / secs / 1e6
+    return {
+        "shape": shape, "storage": storage, "desc": desc, "m": m, "ns": ns, "secs": secs,
+        "mlups": mlups, "mlups_standard": ns * steps / secs_sc / 1e6, "stats": stats,
+        "kernels": {"lb": {"name": names[0], "us_per_launch": t_lb * 1e6, "bytes_per_lu": lb_b,
+                           "gbs": lb_b * ns / t_lb / 1e9},
+                    "ch": {"name": names[1], "us_per_launch": t_ch * 1e6, "launches_per_step": m,
+                           "bytes_per_lu": ch_b, "gbs": ch_b * ns / t_ch / 1e9}},
+        "dominant": {"name": kname, "bytes_per_lu": kbytes, "gbs": achieved},
+        "step_min_bytes_per_lu": step_b, "q": q, "d": d, "es": es,
+    }
+
+
+def run_cpu_baseline(name, budget_s=15.0):
+    """The FP64 oracle on a bounded number of steps of the same workload."""
+    from oracle import orc
+
+    shape, storage, kw, desc = WORKLOADS[name]
+    from paper_0902_3921_amd import hlb
+
+    m = hlb.check_params(0 if len(shape) == 2 else 1, **kw)
+    phi0 = make_inputs(name, shape)
+    ns = 1
+    for s in shape:
+        ns *= s
+    o = orc.Oracle(shape, m=m, **kw).init(phi0)
+    t0 = time.perf_counter()
+    o.step(1)
+    first = time.perf_counter() - t0
+    nsteps = max(1, min(1000, int(budget_s / max(first, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(nsteps)
+    secs = time.perf_counter() - t0
+    return {"value": ns * nsteps / secs / 1e6, "unit": "MLUPS", "cores": orc.threads(), "kind": "oracle",
+            "sample": f"{nsteps} steps of the {desc} workload (FP64 oracle, after 1 untimed step)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="d2q9_spinodal_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="also run a device copy of this many MiB (for the HBM counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU domain decomposition is design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+
+    r = run_gpu(args.workload, args.steps, args.warmup)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+    cpu = None
+    if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
+        cpu = run_cpu_baseline(args.workload)
+
+    ms_per_step = r["secs"] / args.steps * 1e3
+    kd = r["dominant"]
+    out = {
+        "metric": "MLUPS & % HBM peak (D2Q9/D3Q19 hybrid step)",
+        "value": r["mlups"],
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if r["storage"] == "f32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": r["desc"], "lattice": "D2Q9" if r["d"] == 2 else "D3Q19",
+                   "shape": list(r["shape"]), "m": r["m"], "stencil": "N=0.3, Q=2.5",
+                   "params": "a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1", "seed": 0},
+        "roofline": {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": kd["name"],
+                     "bytes_per_lu": kd["bytes_per_lu"]},
+        "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
+        "mlups_standard_stencil": r["mlups_standard"],
+        "kernels": r["kernels"],
+        "check": {"finite": r["stats"]["finite"], "mass": r["stats"]["mass"], "umax": r["stats"]["umax"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

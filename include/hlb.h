@@ -1,0 +1,194 @@
+/*
+ * hlb.h -- C ABI of the MI355X (gfx950) library for the hybrid free-energy
+ * lattice Boltzmann method of Tiribocchi, Stella, Gonnella and Lamura,
+ * "Hybrid lattice Boltzmann model for binary fluid mixtures"
+ * (arXiv:0902.3921).
+ *
+ * One timestep t -> t+1 of a periodic lattice (D2Q9, or the D3Q19
+ * three-dimensional generalisation) computes, from the state (f_t, phi_t):
+ *   1. the force density F = -phi grad(mu), mu = a phi + b phi^3 - kappa lap phi
+ *      (Sec. 2, Eqs. chempot and forza), with the derivatives taken by the
+ *      3x3 stencils of Sec. 2.2 (Eqs. xstencil and laplstencil), parameters
+ *      N and Q; by default in the expanded form
+ *      F = -[(a phi + 3 b phi^3) grad phi - kappa phi grad(lap phi)] that the
+ *      paper analyses in Sec. 3;
+ *   2. the density n = sum f_i and the physical velocity
+ *      n u* = sum f_i e_i + F/2 (Sec. 2.1, Eq. newvel);
+ *   3. the BGK collision with the equilibrium of Eq. espdistrfunc at u* and
+ *      the lattice forcing term of Eq. latticeforceterm, then streaming
+ *      (Eq. forceevoleqn);
+ *   4. m explicit finite-difference substeps of the convection-diffusion
+ *      equation with Delta t_FD = Delta t_LB / m and u*_t held fixed: the
+ *      advection half-step of Eqs. adv, centrdiff, backdiff and fordiff, then
+ *      the diffusion step of Eq. diff (Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ *   - Lattice units: Delta x = Delta t_LB = 1, c_s^2 = 1/3.
+ *   - Sites are indexed idx = x + nx*(y + ny*z), x fastest; nz = 1 for D2Q9.
+ *   - Host field arrays are double precision.  A scalar field holds ns =
+ *     nx*ny*nz values; a vector field holds d*ns values, component-major
+ *     ([component][idx]); populations hold q*ns values ([i][idx]).
+ *   - Velocity order.  D2Q9: 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1)
+ *     5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1).  D3Q19: 0:(0,0,0)
+ *     1:(1,0,0) 2:(-1,0,0) 3:(0,1,0) 4:(0,-1,0) 5:(0,0,1) 6:(0,0,-1)
+ *     7:(1,1,0) 8:(-1,-1,0) 9:(1,-1,0) 10:(-1,1,0) 11:(1,0,1) 12:(-1,0,-1)
+ *     13:(1,0,-1) 14:(-1,0,1) 15:(0,1,1) 16:(0,-1,-1) 17:(0,1,-1) 18:(0,-1,1).
+ *   - Populations are stored on the device as deviations g_i = f_i - w_i rho0
+ *     in double (HLB_F64) or float (HLB_F32_SHIFTED) precision.
+ *   - Device memory: the caller owns one workspace allocation of at least
+ *     hlb_workspace_size() bytes, 256-byte aligned, that outlives the context.
+ *     The library carves every device array out of it and allocates nothing.
+ *   - Streams: all device work of a context is enqueued on the caller's HIP
+ *     stream given at creation (a hipStream_t passed as void*, NULL for the
+ *     default stream).  hlb_step returns without synchronising; calls that
+ *     return host data synchronise the stream before returning.
+ *   - Errors: every call returns an hlb_status and never aborts.
+ *     hlb_last_error() describes the last failure of a context.  Argument
+ *     checks happen on the host before any device work.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef HLB_H
+#define HLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hlb_ctx hlb_ctx;
+
+typedef enum {
+  HLB_OK = 0,
+  HLB_EINVAL = -1,      /* invalid argument or parameter */
+  HLB_ESHAPE = -2,      /* lattice size out of range, or workspace too small */
+  HLB_EUNSTABLE = -3,   /* parameters violate the explicit-stability bound, or max|u*| >= c_s/2 */
+  HLB_ENONFINITE = -4,  /* a non-finite value in the inputs or the state */
+  HLB_EHIP = -5,        /* a HIP runtime call failed */
+  HLB_ESTATE = -6       /* the context is in an error state (after HLB_ENONFINITE) */
+} hlb_status;
+
+typedef enum { HLB_D2Q9 = 0, HLB_D3Q19 = 1 } hlb_lattice;
+
+typedef enum { HLB_F64 = 0, HLB_F32_SHIFTED = 1 } hlb_storage;
+
+/* Model parameters (lattice units). */
+typedef struct {
+  double a, b, kappa;  /* free energy, Sec. 2 Eq. freenergy; b > 0, kappa >= 0 */
+  double tau;          /* BGK relaxation time, Sec. 2.1 Eq. evoleqn; tau > 1/2 */
+  double gamma;        /* mobility Gamma, Sec. 2 Eq. convdiffeqn; >= 0 */
+  double N, Q;         /* force stencils, Sec. 2.2: 2D M = (1-2N)/4, R = (1-Q)/2;
+                          3D M = (1-2N)/8, R = (1-Q)/4 (edge weights) */
+  double cd_Q;         /* Laplacian parameter of the convection-diffusion step;
+                          1 = the standard 5/7-point operator of Sec. 2.3 */
+  int fd_substeps;     /* m = Delta t_LB / Delta t_FD (Sec. 2.3); 0 = the smallest m
+                          with Gamma dt (kappa s^2 + a_eff s) <= 1.8, s the largest
+                          |symbol| of the CH Laplacian, a_eff = -2a (a < 0) or
+                          a + 3b (a >= 0) */
+  int force_form;      /* 1 = expanded form (default), 0 = -phi grad_D(mu) */
+  int advection;       /* 0 = the paper's non-conservative upwind step (default),
+                          1 = conservative upwind face fluxes */
+  int reserved;        /* must be 0 */
+  double g_ext[3];     /* uniform body acceleration: n*g_ext is added to F (Sec. 3) */
+  double rho0;         /* reference density of the stored deviations; > 0 */
+} hlb_params;
+
+/* Global diagnostics at the current time (all sums in double precision,
+ * fixed summation order, so repeated calls give identical results). */
+typedef struct {
+  double mass;      /* sum n */
+  double phi_sum;   /* sum phi */
+  double kinetic;   /* sum n |u*|^2 / 2 */
+  double umax;      /* max |u*| */
+  double mom[3];    /* sum n u* */
+  long long step;   /* timesteps taken since hlb_init_fields / hlb_set_state */
+  int finite;       /* 1 if every population and phi is finite */
+  int reserved;
+} hlb_stats;
+
+/* Fills p with a = -0.1, b = 0.1, kappa = 0.1, tau = 1, Gamma = 1, the paper's
+ * optimal stencil N = 0.3, Q = 2.5 (Sec. 3, Table I), cd_Q = 1, m = 0
+ * (automatic), expanded force, paper advection, g_ext = 0, rho0 = 1. */
+hlb_status hlb_params_default(hlb_params *p);
+
+/* Checks p for lattice `lattice` without touching the device and writes the
+ * number of convection-diffusion substeps m that a context would use.
+ * Returns HLB_EINVAL for invalid values, HLB_EUNSTABLE if an explicit m
+ * violates Gamma dt (kappa s^2 + a_eff s) <= 2. */
+hlb_status hlb_check_params(int lattice, const hlb_params *p, int *m_out);
+
+/* Bytes of device workspace a context of this lattice, storage and size
+ * needs.  Sizes must be >= 1 (nz == 1 for D2Q9) with nx*ny*nz < 2^31;
+ * otherwise HLB_ESHAPE.  Host only. */
+hlb_status hlb_workspace_size(int lattice, int storage, int nx, int ny, int nz, size_t *bytes);
+
+/* Creates a context on the current HIP device.  `workspace` is a device
+ * pointer to `bytes` bytes (>= hlb_workspace_size), `stream` a hipStream_t
+ * or NULL.  The state is undefined until hlb_init_fields or hlb_set_state.
+ * On failure *out is NULL. */
+hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz,
+                      const hlb_params *p, void *workspace, size_t bytes, void *stream);
+
+/* Replaces the parameters between steps (revalidated as hlb_check_params). */
+hlb_status hlb_set_params(hlb_ctx *ctx, const hlb_params *p);
+
+/* Reads the parameters and the resolved m. */
+hlb_status hlb_get_params(const hlb_ctx *ctx, hlb_params *p, int *m_out);
+
+/* Sets phi and f_i = f_i^eq(n, u) (Eq. espdistrfunc) at every site from host
+ * arrays phi[ns], n[ns], u[d*ns]; n or u may be NULL for n = 1, u = 0.
+ * Resets the step counter.  HLB_ENONFINITE if any input is not finite or
+ * n <= 0.  Synchronises the stream. */
+hlb_status hlb_init_fields(hlb_ctx *ctx, const double *phi, const double *n, const double *u);
+
+/* Sets the raw state: populations f[q*ns] (after streaming, before the
+ * collision of the next step) and phi[ns], host double arrays.  Resets the
+ * step counter.  Synchronises. */
+hlb_status hlb_set_state(hlb_ctx *ctx, const double *f, const double *phi);
+
+/* Reads the raw state into host arrays f[q*ns] and phi[ns] (either may be
+ * NULL).  Synchronises. */
+hlb_status hlb_get_state(hlb_ctx *ctx, double *f, double *phi);
+
+/* Enqueues nsteps >= 0 timesteps on the context's stream and returns. */
+hlb_status hlb_step(hlb_ctx *ctx, long long nsteps);
+
+/* Reads the fields at the current time into host arrays (any may be NULL):
+ * n[ns] = sum f_i, u[d*ns] = u* of Eq. newvel, phi[ns], and mu[ns] =
+ * a phi + b phi^3 - kappa lap_D phi with the force stencil (Eq. chempot).
+ * Synchronises. */
+hlb_status hlb_get_fields(hlb_ctx *ctx, double *n, double *u, double *phi, double *mu);
+
+/* Computes the global diagnostics on the device and copies them to *out.
+ * Returns HLB_ENONFINITE (and puts the context in the error state) if the
+ * state holds a non-finite value, HLB_EUNSTABLE if max|u*| >= c_s/2 (the
+ * low-Mach condition of Sec. 2.1); *out is filled in both cases.
+ * Synchronises. */
+hlb_status hlb_reduce(hlb_ctx *ctx, hlb_stats *out);
+
+/* Runs nsteps timesteps like hlb_step, recording HIP events around every
+ * kernel launch on the context's stream, synchronises, and writes the
+ * summed kernel time in milliseconds per kernel class:
+ *   ms[0] = force + collide-and-stream kernel, ms[1] = convection-diffusion
+ *   kernels.  Intended for benchmarks; slower than hlb_step. */
+hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
+
+/* Names of the device kernels of a kernel class (0 or 1) for the context's
+ * lattice and storage, as they appear in profiler traces. */
+const char *hlb_kernel_name(const hlb_ctx *ctx, int kernel_class);
+
+/* Message of the context's last failure ("" if none); owned by the context,
+ * valid until its next call.  ctx may be NULL for failures of hlb_create. */
+const char *hlb_last_error(const hlb_ctx *ctx);
+
+/* Destroys the context.  Does not free the workspace. */
+hlb_status hlb_destroy(hlb_ctx *ctx);
+
+/* Library version string. */
+const char *hlb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HLB_H */

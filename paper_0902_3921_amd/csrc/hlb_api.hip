@@ -1,0 +1,696 @@
+// hlb_api.hip -- host side of the C ABI declared in include/hlb.h: parameter
+// validation, workspace layout, kernel dispatch on the caller's stream.
+//
+// The host never synchronises inside hlb_step; every launch goes to the
+// context's stream in order: for each timestep the fused force +
+// collide-and-stream kernel (reads g_t, phi_t; writes g_{t+1}, u*_t), then m
+// convection-diffusion substeps ping-ponging between the two phi buffers.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hlb.h"
+#include "kernels.hpp"
+
+using namespace hlb;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Tile shapes of the stencil kernels, per lattice and storage type.
+template <class L, typename T> struct Tiles;
+template <> struct Tiles<D2Q9, double> {
+  static constexpr int LB[3] = {64, 8, 1};
+  static constexpr int CH[3] = {64, 8, 1};
+};
+template <> struct Tiles<D2Q9, float> {
+  static constexpr int LB[3] = {64, 8, 1};
+  static constexpr int CH[3] = {64, 16, 1};
+};
+template <> struct Tiles<D3Q19, double> {
+  static constexpr int LB[3] = {32, 4, 4};
+  static constexpr int CH[3] = {16, 4, 4};
+};
+template <> struct Tiles<D3Q19, float> {
+  static constexpr int LB[3] = {32, 4, 4};
+  static constexpr int CH[3] = {32, 4, 4};
+};
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+struct Layout {
+  size_t g[2], phi[2], u, io, part, out, total;
+  int nblk_reduce;
+};
+
+int lattice_d(int lattice) { return lattice == HLB_D2Q9 ? 2 : 3; }
+int lattice_q(int lattice) { return lattice == HLB_D2Q9 ? 9 : 19; }
+
+// Blocks of the reduction kernel (it uses the force-kernel tile).
+int reduce_blocks(int lattice, int storage, int nx, int ny, int nz) {
+  const int *t;
+  if (lattice == HLB_D2Q9)
+    t = storage == HLB_F64 ? Tiles<D2Q9, double>::LB : Tiles<D2Q9, float>::LB;
+  else
+    t = storage == HLB_F64 ? Tiles<D3Q19, double>::LB : Tiles<D3Q19, float>::LB;
+  return ceil_div(nx, t[0]) * ceil_div(ny, t[1]) * ceil_div(nz, t[2]);
+}
+
+hlb_status check_shape(int lattice, int storage, int nx, int ny, int nz, std::string *msg) {
+  if (lattice != HLB_D2Q9 && lattice != HLB_D3Q19) {
+    *msg = "lattice must be HLB_D2Q9 or HLB_D3Q19";
+    return HLB_EINVAL;
+  }
+  if (storage != HLB_F64 && storage != HLB_F32_SHIFTED) {
+    *msg = "storage must be HLB_F64 or HLB_F32_SHIFTED";
+    return HLB_EINVAL;
+  }
+  if (nx < 1 || ny < 1 || nz < 1 || (lattice == HLB_D2Q9 && nz != 1)) {
+    *msg = "lattice sizes must be >= 1, with nz == 1 for D2Q9";
+    return HLB_ESHAPE;
+  }
+  const long long ns = (long long)nx * ny * nz;
+  if (ns >= (1LL << 31)) {
+    *msg = "nx*ny*nz must be < 2^31";
+    return HLB_ESHAPE;
+  }
+  return HLB_OK;
+}
+
+Layout make_layout(int lattice, int storage, int nx, int ny, int nz) {
+  Layout L{};
+  const size_t ns = (size_t)nx * ny * nz;
+  const size_t es = storage == HLB_F64 ? 8 : 4;
+  const size_t q = lattice_q(lattice), d = lattice_d(lattice);
+  size_t off = 0;
+  for (int k = 0; k < 2; k++) {
+    L.g[k] = off;
+    off = align_up(off + q * ns * es);
+  }
+  for (int k = 0; k < 2; k++) {
+    L.phi[k] = off;
+    off = align_up(off + ns * es);
+  }
+  L.u = off;
+  off = align_up(off + d * ns * es);
+  L.io = off;  // double precision staging: [n | u (d) | phi | mu]
+  off = align_up(off + (3 + d) * ns * 8);
+  L.nblk_reduce = reduce_blocks(lattice, storage, nx, ny, nz);
+  L.part = off;
+  off = align_up(off + (size_t)L.nblk_reduce * 8 * 8);
+  L.out = off;
+  off = align_up(off + 8 * 8);
+  L.total = off;
+  return L;
+}
+
+bool finite_all(const double *v, size_t n) {
+  for (size_t i = 0; i < n; i++)
+    if (!std::isfinite(v[i])) return false;
+  return true;
+}
+
+// Largest |symbol| of the Laplacian stencil with face weight Q (the symbol is
+// multilinear in cos k, so its extremes are at the corners of [-1,1]^d).
+// Returns false if the symbol is positive somewhere (not a diffusion operator).
+bool lap_symbol_range(int d, double Q, double *smax_abs) {
+  const double R = d == 2 ? (1.0 - Q) / 2.0 : (1.0 - Q) / 4.0;
+  double lo = 0.0, hi = -1e300;
+  const int ncorner = 1 << d;
+  for (int c = 0; c < ncorner; c++) {
+    double cs[3] = {1, 1, 1};
+    for (int k = 0; k < d; k++) cs[k] = (c >> k) & 1 ? -1.0 : 1.0;
+    double sum = 0, pairs = 0;
+    for (int k = 0; k < d; k++) sum += cs[k];
+    for (int i = 0; i < d; i++)
+      for (int j = i + 1; j < d; j++) pairs += cs[i] * cs[j];
+    const double centre = d == 2 ? 4.0 * (Q + R) : 6.0 * Q + 12.0 * R;
+    const double s = 2.0 * Q * sum + 4.0 * R * pairs - centre;
+    lo = std::min(lo, s);
+    hi = std::max(hi, s);
+  }
+  *smax_abs = -lo;
+  return hi <= 1e-12;
+}
+
+hlb_status validate(int lattice, const hlb_params *p, int *m_out, std::string *msg) {
+  if (!p) {
+    *msg = "params is NULL";
+    return HLB_EINVAL;
+  }
+  const double vals[] = {p->a,     p->b, p->kappa,    p->tau,      p->gamma,    p->N,   p->Q,
+                         p->cd_Q, p->rho0, p->g_ext[0], p->g_ext[1], p->g_ext[2]};
+  for (double v : vals)
+    if (!std::isfinite(v)) {
+      *msg = "parameters must be finite";
+      return HLB_EINVAL;
+    }
+  if (!(p->tau > 0.5)) {
+    *msg = "tau must be > 1/2 (positive viscosity)";
+    return HLB_EINVAL;
+  }
+  if (!(p->b > 0)) {
+    *msg = "b must be > 0";
+    return HLB_EINVAL;
+  }
+  if (p->kappa < 0 || p->gamma < 0) {
+    *msg = "kappa and gamma must be >= 0";
+    return HLB_EINVAL;
+  }
+  if (!(p->rho0 > 0)) {
+    *msg = "rho0 must be > 0";
+    return HLB_EINVAL;
+  }
+  if (p->force_form != 0 && p->force_form != 1) {
+    *msg = "force_form must be 0 or 1";
+    return HLB_EINVAL;
+  }
+  if (p->advection != 0 && p->advection != 1) {
+    *msg = "advection must be 0 or 1";
+    return HLB_EINVAL;
+  }
+  if (p->fd_substeps < 0 || p->reserved != 0) {
+    *msg = "fd_substeps must be >= 0 and reserved 0";
+    return HLB_EINVAL;
+  }
+  const int d = lattice_d(lattice);
+  if (d == 2 && p->g_ext[2] != 0.0) {
+    *msg = "g_ext[2] must be 0 for D2Q9";
+    return HLB_EINVAL;
+  }
+  double smax;
+  if (!lap_symbol_range(d, p->cd_Q, &smax)) {
+    *msg = "cd_Q gives a convection-diffusion Laplacian with a positive symbol";
+    return HLB_EINVAL;
+  }
+  // checkerboard bound of the explicit diffusion step, Gamma dt (kappa s^2 + a_eff s) <= 2
+  const double a_eff = p->a < 0 ? -2.0 * p->a : p->a + 3.0 * p->b;
+  const double rate = p->gamma * (p->kappa * smax * smax + a_eff * smax);
+  int m = p->fd_substeps;
+  if (m == 0) {
+    m = std::max(1, (int)std::ceil(rate / 1.8 - 1e-12));
+  } else if (rate / m > 2.0 + 1e-12) {
+    char buf[200];
+    snprintf(buf, sizeof buf, "fd_substeps = %d violates the stability bound (needs m >= %d)", m,
+             (int)std::ceil(rate / 2.0 - 1e-12));
+    *msg = buf;
+    return HLB_EUNSTABLE;
+  }
+  if (m_out) *m_out = m;
+  return HLB_OK;
+}
+
+}  // namespace
+
+struct hlb_ctx {
+  int lattice, storage, d, q, nx, ny, nz;
+  long long ns;
+  hlb_params p;
+  int m;
+  hipStream_t stream;
+  int device;
+  char *ws;
+  size_t ws_bytes;
+  Layout lay;
+  int gcur, phicur;
+  long long step;
+  bool error_state;
+  std::string err;
+  std::string names[2];
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+hlb_status fail(hlb_ctx *c, hlb_status s, const std::string &msg) {
+  if (c) c->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+hlb_status hip_fail(hlb_ctx *c, hipError_t e, const char *what) {
+  return fail(c, HLB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+KParams kparams(const hlb_ctx *c) {
+  KParams k{};
+  k.nx = c->nx;
+  k.ny = c->ny;
+  k.nz = c->nz;
+  k.ns = (int)c->ns;
+  k.a = c->p.a;
+  k.b = c->p.b;
+  k.kappa = c->p.kappa;
+  k.omega = 1.0 / c->p.tau;
+  k.gamma = c->p.gamma;
+  if (c->d == 2) {
+    k.gN = c->p.N;
+    k.gM = (1.0 - 2.0 * c->p.N) / 4.0;
+    k.lQ = c->p.Q;
+    k.lR = (1.0 - c->p.Q) / 2.0;
+    k.lC = -4.0 * (k.lQ + k.lR);
+    k.cQ = c->p.cd_Q;
+    k.cR = (1.0 - c->p.cd_Q) / 2.0;
+    k.cC = -4.0 * (k.cQ + k.cR);
+  } else {
+    k.gN = c->p.N;
+    k.gM = (1.0 - 2.0 * c->p.N) / 8.0;
+    k.lQ = c->p.Q;
+    k.lR = (1.0 - c->p.Q) / 4.0;
+    k.lC = -(6.0 * k.lQ + 12.0 * k.lR);
+    k.cQ = c->p.cd_Q;
+    k.cR = (1.0 - c->p.cd_Q) / 4.0;
+    k.cC = -(6.0 * k.cQ + 12.0 * k.cR);
+  }
+  k.dt = 1.0 / c->m;
+  for (int i = 0; i < 3; i++) k.g[i] = c->p.g_ext[i];
+  k.rho0 = c->p.rho0;
+  k.force_form = c->p.force_form;
+  k.advection = c->p.advection;
+  return k;
+}
+
+template <class T> T *at(hlb_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
+
+dim3 tile_grid(const hlb_ctx *c, const int t[3]) {
+  return dim3(ceil_div(c->nx, t[0]), ceil_div(c->ny, t[1]), ceil_div(c->nz, t[2]));
+}
+
+// Per-(lattice, storage) launches.
+template <class L, typename T>
+struct Ops {
+  using TL = Tiles<L, T>;
+  static constexpr int LB0 = TL::LB[0], LB1 = TL::LB[1], LB2 = TL::LB[2];
+  static constexpr int CH0 = TL::CH[0], CH1 = TL::CH[1], CH2 = TL::CH[2];
+
+  static void lb(hlb_ctx *c, const KParams &k) {
+    const T *gin = at<T>(c, c->lay.g[c->gcur]);
+    T *gout = at<T>(c, c->lay.g[1 - c->gcur]);
+    hipLaunchKernelGGL((k_lb<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k, gin, gout,
+                       at<T>(c, c->lay.phi[c->phicur]), at<T>(c, c->lay.u));
+  }
+  static void ch(hlb_ctx *c, const KParams &k) {
+    hipLaunchKernelGGL((k_ch<L, T, CH0, CH1, CH2>), tile_grid(c, TL::CH), dim3(256), 0, c->stream, k,
+                       at<T>(c, c->lay.phi[c->phicur]), at<T>(c, c->lay.u), at<T>(c, c->lay.phi[1 - c->phicur]));
+  }
+  static void init(hlb_ctx *c, const KParams &k) {
+    const unsigned nb = (unsigned)((c->ns + 255) / 256);
+    hipLaunchKernelGGL((k_init<L, T>), dim3(nb), dim3(256), 0, c->stream, k, at<double>(c, c->lay.io),
+                       at<T>(c, c->lay.g[c->gcur]), at<T>(c, c->lay.phi[c->phicur]));
+  }
+  static void readout(hlb_ctx *c, const KParams &k) {
+    hipLaunchKernelGGL((k_readout<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k,
+                       at<T>(c, c->lay.g[c->gcur]), at<T>(c, c->lay.phi[c->phicur]), at<double>(c, c->lay.io));
+  }
+  static void reduce(hlb_ctx *c, const KParams &k) {
+    hipLaunchKernelGGL((k_reduce<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k,
+                       at<T>(c, c->lay.g[c->gcur]), at<T>(c, c->lay.phi[c->phicur]), at<double>(c, c->lay.part));
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, c->stream, c->lay.nblk_reduce,
+                       at<double>(c, c->lay.part), at<double>(c, c->lay.out));
+  }
+  static void get_pop(hlb_ctx *c, const KParams &k, int i) {
+    const unsigned nb = (unsigned)((c->ns + 255) / 256);
+    hipLaunchKernelGGL((k_get_pop<T>), dim3(nb), dim3(256), 0, c->stream, k,
+                       at<T>(c, c->lay.g[c->gcur]) + (size_t)i * c->ns, L::e(i, 0), L::e(i, 1), L::e(i, 2), L::w(i),
+                       at<double>(c, c->lay.io));
+  }
+  static void set_pop(hlb_ctx *c, const KParams &k, int i) {
+    const unsigned nb = (unsigned)((c->ns + 255) / 256);
+    hipLaunchKernelGGL((k_set_pop<T>), dim3(nb), dim3(256), 0, c->stream, k, at<double>(c, c->lay.io), L::e(i, 0),
+                       L::e(i, 1), L::e(i, 2), L::w(i), at<T>(c, c->lay.g[c->gcur]) + (size_t)i * c->ns);
+  }
+  static void to_phi(hlb_ctx *c) {
+    const unsigned nb = (unsigned)((c->ns + 255) / 256);
+    hipLaunchKernelGGL((k_convert<T>), dim3(nb), dim3(256), 0, c->stream, (int)c->ns, at<double>(c, c->lay.io),
+                       at<T>(c, c->lay.phi[c->phicur]));
+  }
+  static void from_phi(hlb_ctx *c) {
+    const unsigned nb = (unsigned)((c->ns + 255) / 256);
+    hipLaunchKernelGGL((k_widen<T>), dim3(nb), dim3(256), 0, c->stream, (int)c->ns,
+                       at<T>(c, c->lay.phi[c->phicur]), at<double>(c, c->lay.io));
+  }
+};
+
+template <typename F>
+void dispatch(hlb_ctx *c, F &&fn) {
+  if (c->lattice == HLB_D2Q9) {
+    if (c->storage == HLB_F64) fn(Ops<D2Q9, double>{});
+    else fn(Ops<D2Q9, float>{});
+  } else {
+    if (c->storage == HLB_F64) fn(Ops<D3Q19, double>{});
+    else fn(Ops<D3Q19, float>{});
+  }
+}
+
+hlb_status launch_check(hlb_ctx *c, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(c, e, what);
+  return HLB_OK;
+}
+
+hlb_status sync(hlb_ctx *c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipStreamSynchronize");
+  return HLB_OK;
+}
+
+hlb_status usable(hlb_ctx *c) {
+  if (!c) return HLB_EINVAL;
+  if (c->error_state) return fail(c, HLB_ESTATE, "context is in the error state after a non-finite state");
+  return HLB_OK;
+}
+
+// One timestep: force + collide-and-stream, then m convection-diffusion substeps.
+void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
+  dispatch(c, [&](auto ops) {
+    if (ev) (void)hipEventRecord(ev[0], c->stream);
+    ops.lb(c, k);
+    if (ev) (void)hipEventRecord(ev[1], c->stream);
+    for (int s = 0; s < c->m; s++) {
+      ops.ch(c, k);
+      c->phicur = 1 - c->phicur;
+    }
+    if (ev) (void)hipEventRecord(ev[2], c->stream);
+  });
+  c->gcur = 1 - c->gcur;
+  c->step++;
+}
+
+std::string kernel_names(int lattice, int storage, int cls) {
+  const char *lat = lattice == HLB_D2Q9 ? "D2Q9" : "D3Q19";
+  const char *ty = storage == HLB_F64 ? "double" : "float";
+  char buf[160];
+  snprintf(buf, sizeof buf, "%s<hlb::%s, %s, ...>", cls == 0 ? "hlb::k_lb" : "hlb::k_ch", lat, ty);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+hlb_status hlb_params_default(hlb_params *p) {
+  if (!p) return HLB_EINVAL;
+  std::memset(p, 0, sizeof *p);
+  p->a = -0.1;
+  p->b = 0.1;
+  p->kappa = 0.1;
+  p->tau = 1.0;
+  p->gamma = 1.0;
+  p->N = 0.3;
+  p->Q = 2.5;
+  p->cd_Q = 1.0;
+  p->fd_substeps = 0;
+  p->force_form = 1;
+  p->advection = 0;
+  p->rho0 = 1.0;
+  return HLB_OK;
+}
+
+hlb_status hlb_check_params(int lattice, const hlb_params *p, int *m_out) {
+  std::string msg;
+  if (lattice != HLB_D2Q9 && lattice != HLB_D3Q19) return fail(nullptr, HLB_EINVAL, "invalid lattice");
+  hlb_status s = validate(lattice, p, m_out, &msg);
+  if (s != HLB_OK) return fail(nullptr, s, msg);
+  return HLB_OK;
+}
+
+hlb_status hlb_workspace_size(int lattice, int storage, int nx, int ny, int nz, size_t *bytes) {
+  std::string msg;
+  if (!bytes) return fail(nullptr, HLB_EINVAL, "bytes is NULL");
+  hlb_status s = check_shape(lattice, storage, nx, ny, nz, &msg);
+  if (s != HLB_OK) return fail(nullptr, s, msg);
+  *bytes = make_layout(lattice, storage, nx, ny, nz).total;
+  return HLB_OK;
+}
+
+hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz, const hlb_params *p,
+                      void *workspace, size_t bytes, void *stream) {
+  std::string msg;
+  if (!out) return fail(nullptr, HLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  hlb_status s = check_shape(lattice, storage, nx, ny, nz, &msg);
+  if (s != HLB_OK) return fail(nullptr, s, msg);
+  int m = 0;
+  s = validate(lattice, p, &m, &msg);
+  if (s != HLB_OK) return fail(nullptr, s, msg);
+  const Layout lay = make_layout(lattice, storage, nx, ny, nz);
+  if (!workspace || bytes < lay.total) return fail(nullptr, HLB_ESHAPE, "workspace missing or too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return fail(nullptr, HLB_EINVAL, "workspace must be 256-byte aligned");
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(nullptr, HLB_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  hipPointerAttribute_t attr;
+  e = hipPointerGetAttributes(&attr, workspace);
+  if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
+    return fail(nullptr, HLB_EINVAL, "workspace is not device memory");
+  hlb_ctx *c = new (std::nothrow) hlb_ctx();
+  if (!c) return fail(nullptr, HLB_EINVAL, "out of host memory");
+  c->lattice = lattice;
+  c->storage = storage;
+  c->d = lattice_d(lattice);
+  c->q = lattice_q(lattice);
+  c->nx = nx;
+  c->ny = ny;
+  c->nz = nz;
+  c->ns = (long long)nx * ny * nz;
+  c->p = *p;
+  c->m = m;
+  c->stream = reinterpret_cast<hipStream_t>(stream);
+  c->device = dev;
+  c->ws = reinterpret_cast<char *>(workspace);
+  c->ws_bytes = bytes;
+  c->lay = lay;
+  c->gcur = 0;
+  c->phicur = 0;
+  c->step = 0;
+  c->error_state = false;
+  c->names[0] = kernel_names(lattice, storage, 0);
+  c->names[1] = kernel_names(lattice, storage, 1);
+  *out = c;
+  return HLB_OK;
+}
+
+hlb_status hlb_set_params(hlb_ctx *c, const hlb_params *p) {
+  if (!c) return HLB_EINVAL;
+  std::string msg;
+  int m = 0;
+  hlb_status s = validate(c->lattice, p, &m, &msg);
+  if (s != HLB_OK) return fail(c, s, msg);
+  c->p = *p;
+  c->m = m;
+  return HLB_OK;
+}
+
+hlb_status hlb_get_params(const hlb_ctx *c, hlb_params *p, int *m_out) {
+  if (!c) return HLB_EINVAL;
+  if (p) *p = c->p;
+  if (m_out) *m_out = c->m;
+  return HLB_OK;
+}
+
+hlb_status hlb_init_fields(hlb_ctx *c, const double *phi, const double *n, const double *u) {
+  if (!c) return HLB_EINVAL;
+  if (!phi) return fail(c, HLB_EINVAL, "phi is NULL");
+  const size_t ns = (size_t)c->ns;
+  std::vector<double> host((2 + c->d) * ns);
+  std::memcpy(host.data(), phi, ns * 8);
+  if (n) std::memcpy(host.data() + ns, n, ns * 8);
+  else std::fill(host.begin() + ns, host.begin() + 2 * ns, 1.0);
+  if (u) std::memcpy(host.data() + 2 * ns, u, c->d * ns * 8);
+  else std::fill(host.begin() + 2 * ns, host.end(), 0.0);
+  if (!finite_all(host.data(), host.size())) return fail(c, HLB_ENONFINITE, "non-finite value in the initial fields");
+  for (size_t i = 0; i < ns; i++)
+    if (!(host[ns + i] > 0)) return fail(c, HLB_ENONFINITE, "initial density must be > 0");
+  hipError_t e = hipMemcpyAsync(at<double>(c, c->lay.io), host.data(), host.size() * 8, hipMemcpyHostToDevice,
+                                c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  c->gcur = 0;
+  c->phicur = 0;
+  const KParams k = kparams(c);
+  dispatch(c, [&](auto ops) { ops.init(c, k); });
+  hlb_status s = launch_check(c, "init kernel");
+  if (s != HLB_OK) return s;
+  s = sync(c);
+  if (s != HLB_OK) return s;
+  c->step = 0;
+  c->error_state = false;
+  return HLB_OK;
+}
+
+hlb_status hlb_set_state(hlb_ctx *c, const double *f, const double *phi) {
+  if (!c) return HLB_EINVAL;
+  if (!f || !phi) return fail(c, HLB_EINVAL, "f and phi must not be NULL");
+  const size_t ns = (size_t)c->ns;
+  if (!finite_all(f, c->q * ns) || !finite_all(phi, ns))
+    return fail(c, HLB_ENONFINITE, "non-finite value in the state");
+  c->gcur = 0;
+  c->phicur = 0;
+  const KParams k = kparams(c);
+  double *io = at<double>(c, c->lay.io);
+  for (int i = 0; i < c->q; i++) {
+    hipError_t e = hipMemcpyAsync(io, f + (size_t)i * ns, ns * 8, hipMemcpyHostToDevice, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    dispatch(c, [&](auto ops) { ops.set_pop(c, k, i); });
+    hlb_status s = launch_check(c, "set_pop kernel");
+    if (s != HLB_OK) return s;
+    s = sync(c);  // io is reused by the next population
+    if (s != HLB_OK) return s;
+  }
+  hipError_t e = hipMemcpyAsync(io, phi, ns * 8, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  dispatch(c, [&](auto ops) { ops.to_phi(c); });
+  hlb_status s = launch_check(c, "convert kernel");
+  if (s != HLB_OK) return s;
+  s = sync(c);
+  if (s != HLB_OK) return s;
+  c->step = 0;
+  c->error_state = false;
+  return HLB_OK;
+}
+
+hlb_status hlb_get_state(hlb_ctx *c, double *f, double *phi) {
+  if (!c) return HLB_EINVAL;
+  const size_t ns = (size_t)c->ns;
+  const KParams k = kparams(c);
+  double *io = at<double>(c, c->lay.io);
+  if (f) {
+    for (int i = 0; i < c->q; i++) {
+      dispatch(c, [&](auto ops) { ops.get_pop(c, k, i); });
+      hlb_status s = launch_check(c, "get_pop kernel");
+      if (s != HLB_OK) return s;
+      hipError_t e = hipMemcpyAsync(f + (size_t)i * ns, io, ns * 8, hipMemcpyDeviceToHost, c->stream);
+      if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+      s = sync(c);
+      if (s != HLB_OK) return s;
+    }
+  }
+  if (phi) {
+    dispatch(c, [&](auto ops) { ops.from_phi(c); });
+    hlb_status s = launch_check(c, "widen kernel");
+    if (s != HLB_OK) return s;
+    hipError_t e = hipMemcpyAsync(phi, io, ns * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+    s = sync(c);
+    if (s != HLB_OK) return s;
+  }
+  return HLB_OK;
+}
+
+hlb_status hlb_step(hlb_ctx *c, long long nsteps) {
+  hlb_status s = usable(c);
+  if (s != HLB_OK) return s;
+  if (nsteps < 0) return fail(c, HLB_EINVAL, "nsteps must be >= 0");
+  const KParams k = kparams(c);
+  for (long long t = 0; t < nsteps; t++) enqueue_step(c, k, nullptr);
+  return launch_check(c, "step kernels");
+}
+
+hlb_status hlb_step_timed(hlb_ctx *c, long long nsteps, double ms[2]) {
+  hlb_status s = usable(c);
+  if (s != HLB_OK) return s;
+  if (nsteps < 0 || !ms) return fail(c, HLB_EINVAL, "nsteps must be >= 0 and ms non-NULL");
+  ms[0] = ms[1] = 0.0;
+  constexpr int kChunk = 64;
+  std::vector<hipEvent_t> ev(3 * kChunk);
+  for (auto &e : ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_fail(c, r, "hipEventCreate");
+  }
+  const KParams k = kparams(c);
+  long long done = 0;
+  hlb_status st = HLB_OK;
+  while (done < nsteps && st == HLB_OK) {
+    const int n = (int)std::min<long long>(kChunk, nsteps - done);
+    for (int t = 0; t < n; t++) enqueue_step(c, k, &ev[3 * t]);
+    st = launch_check(c, "step kernels");
+    if (st != HLB_OK) break;
+    st = sync(c);
+    if (st != HLB_OK) break;
+    for (int t = 0; t < n; t++) {
+      float a = 0, b = 0;
+      (void)hipEventElapsedTime(&a, ev[3 * t], ev[3 * t + 1]);
+      (void)hipEventElapsedTime(&b, ev[3 * t + 1], ev[3 * t + 2]);
+      ms[0] += a;
+      ms[1] += b;
+    }
+    done += n;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  return st;
+}
+
+hlb_status hlb_get_fields(hlb_ctx *c, double *n, double *u, double *phi, double *mu) {
+  if (!c) return HLB_EINVAL;
+  const size_t ns = (size_t)c->ns;
+  const KParams k = kparams(c);
+  dispatch(c, [&](auto ops) { ops.readout(c, k); });
+  hlb_status s = launch_check(c, "readout kernel");
+  if (s != HLB_OK) return s;
+  const double *io = at<double>(c, c->lay.io);
+  struct Part {
+    double *dst;
+    size_t off, count;
+  } parts[4] = {{n, 0, ns}, {u, ns, c->d * ns}, {phi, (1 + c->d) * ns, ns}, {mu, (2 + c->d) * ns, ns}};
+  for (auto &pt : parts) {
+    if (!pt.dst) continue;
+    hipError_t e = hipMemcpyAsync(pt.dst, io + pt.off, pt.count * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  }
+  return sync(c);
+}
+
+hlb_status hlb_reduce(hlb_ctx *c, hlb_stats *out) {
+  if (!c || !out) return HLB_EINVAL;
+  const KParams k = kparams(c);
+  dispatch(c, [&](auto ops) { ops.reduce(c, k); });
+  hlb_status s = launch_check(c, "reduce kernels");
+  if (s != HLB_OK) return s;
+  double r[8];
+  hipError_t e = hipMemcpyAsync(r, at<double>(c, c->lay.out), sizeof r, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  s = sync(c);
+  if (s != HLB_OK) return s;
+  std::memset(out, 0, sizeof *out);
+  out->mass = r[0];
+  out->phi_sum = r[1];
+  out->kinetic = r[2];
+  out->mom[0] = r[3];
+  out->mom[1] = r[4];
+  out->mom[2] = r[5];
+  out->umax = r[6];
+  out->step = c->step;
+  out->finite = r[7] == 0.0 ? 1 : 0;
+  if (!out->finite) {
+    c->error_state = true;
+    return fail(c, HLB_ENONFINITE, "the state holds a non-finite value");
+  }
+  if (out->umax >= 0.5 * std::sqrt(1.0 / 3.0))
+    return fail(c, HLB_EUNSTABLE, "max|u*| >= c_s/2: outside the low-Mach regime of the scheme");
+  return HLB_OK;
+}
+
+const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
+  if (!c || cls < 0 || cls > 1) return "";
+  return c->names[cls].c_str();
+}
+
+const char *hlb_last_error(const hlb_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+hlb_status hlb_destroy(hlb_ctx *c) {
+  delete c;
+  return HLB_OK;
+}
+
+const char *hlb_version(void) { return "hlb 0.1.0 (gfx950)"; }
+
+}  // extern "C"

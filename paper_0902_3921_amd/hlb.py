@@ -1,0 +1,268 @@
+"""Python binding of ``libhlb.so`` (the C ABI in ``include/hlb.h``).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  PyTorch supplies the device workspace (one uint8 tensor) and
+the stream; nothing here computes on the fields.  Loading fails loudly if the
+library has not been built (``python -m paper_0902_3921_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhlb.so")
+
+HLB_OK, HLB_EINVAL, HLB_ESHAPE, HLB_EUNSTABLE, HLB_ENONFINITE, HLB_EHIP, HLB_ESTATE = 0, -1, -2, -3, -4, -5, -6
+D2Q9, D3Q19 = 0, 1
+F64, F32_SHIFTED = 0, 1
+_STORAGE = {"f64": F64, "f32": F32_SHIFTED, F64: F64, F32_SHIFTED: F32_SHIFTED}
+
+STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ESHAPE", -3: "HLB_EUNSTABLE",
+                -4: "HLB_ENONFINITE", -5: "HLB_EHIP", -6: "HLB_ESTATE"}
+
+# every symbol include/hlb.h declares
+EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_create",
+           "hlb_set_params", "hlb_get_params", "hlb_init_fields", "hlb_set_state", "hlb_get_state",
+           "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name",
+           "hlb_last_error", "hlb_destroy", "hlb_version")
+
+
+class HlbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("a", ctypes.c_double), ("b", ctypes.c_double), ("kappa", ctypes.c_double),
+        ("tau", ctypes.c_double), ("gamma", ctypes.c_double),
+        ("N", ctypes.c_double), ("Q", ctypes.c_double), ("cd_Q", ctypes.c_double),
+        ("fd_substeps", ctypes.c_int), ("force_form", ctypes.c_int), ("advection", ctypes.c_int),
+        ("reserved", ctypes.c_int),
+        ("g_ext", ctypes.c_double * 3), ("rho0", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("phi_sum", ctypes.c_double), ("kinetic", ctypes.c_double),
+        ("umax", ctypes.c_double), ("mom", ctypes.c_double * 3), ("step", ctypes.c_longlong),
+        ("finite", ctypes.c_int), ("reserved", ctypes.c_int),
+    ]
+
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+def load():
+    """Load libhlb.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_0902_3921_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    st = ctypes.c_int
+    sig = {
+        "hlb_params_default": (st, [ctypes.POINTER(Params)]),
+        "hlb_check_params": (st, [ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int)]),
+        "hlb_workspace_size": (st, [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_size_t)]),
+        "hlb_create": (st, [ctypes.POINTER(_vp)] + [ctypes.c_int] * 5
+                       + [ctypes.POINTER(Params), _vp, ctypes.c_size_t, _vp]),
+        "hlb_set_params": (st, [_vp, ctypes.POINTER(Params)]),
+        "hlb_get_params": (st, [_vp, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int)]),
+        "hlb_init_fields": (st, [_vp, _dp, _dp, _dp]),
+        "hlb_set_state": (st, [_vp, _dp, _dp]),
+        "hlb_get_state": (st, [_vp, _dp, _dp]),
+        "hlb_step": (st, [_vp, ctypes.c_longlong]),
+        "hlb_get_fields": (st, [_vp, _dp, _dp, _dp, _dp]),
+        "hlb_reduce": (st, [_vp, ctypes.POINTER(Stats)]),
+        "hlb_step_timed": (st, [_vp, ctypes.c_longlong, _dp]),
+        "hlb_kernel_name": (ctypes.c_char_p, [_vp, ctypes.c_int]),
+        "hlb_last_error": (ctypes.c_char_p, [_vp]),
+        "hlb_destroy": (st, [_vp]),
+        "hlb_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, ctx=None):
+    if status != HLB_OK:
+        msg = load().hlb_last_error(ctx).decode()
+        raise HlbError(status, msg)
+
+
+def lattice_of(shape) -> int:
+    if len(shape) == 2:
+        return D2Q9
+    if len(shape) == 3:
+        return D3Q19
+    raise ValueError("lattice shape must be (ny, nx) or (nz, ny, nx)")
+
+
+def _dims(shape):
+    shape = tuple(int(s) for s in shape)
+    return (shape[1], shape[0], 1) if len(shape) == 2 else (shape[2], shape[1], shape[0])
+
+
+def params(**kw) -> Params:
+    """hlb_params with the library defaults, then the given fields."""
+    p = Params()
+    _check(load().hlb_params_default(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k in ("g_ext", "g"):
+            for i in range(3):
+                p.g_ext[i] = float(v[i]) if i < len(v) else 0.0
+        elif k in ("m", "fd_substeps"):
+            p.fd_substeps = int(v)
+        else:
+            if not hasattr(p, k):
+                raise TypeError(f"unknown parameter {k}")
+            setattr(p, k, type(getattr(p, k))(v))
+    return p
+
+
+def check_params(lattice: int, **kw) -> int:
+    """Validate parameters on the host; returns the substep count m."""
+    m = ctypes.c_int()
+    _check(load().hlb_check_params(lattice, ctypes.byref(params(**kw)), ctypes.byref(m)))
+    return m.value
+
+
+def workspace_size(lattice: int, storage, nx: int, ny: int, nz: int = 1) -> int:
+    b = ctypes.c_size_t()
+    _check(load().hlb_workspace_size(lattice, _STORAGE[storage], nx, ny, nz, ctypes.byref(b)))
+    return b.value
+
+
+def version() -> str:
+    return load().hlb_version().decode()
+
+
+def _f64(a, shape) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if a.size != int(np.prod(shape)):
+        raise ValueError(f"expected {int(np.prod(shape))} values, got {a.size}")
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+class Sim:
+    """One periodic simulation on the current HIP device.
+
+    ``shape`` is ``(ny, nx)`` (D2Q9) or ``(nz, ny, nx)`` (D3Q19); ``storage``
+    is ``"f64"`` or ``"f32"`` (populations stored as float deviations from
+    w_i rho0).  Keyword arguments set ``hlb_params`` fields (``m`` is an alias
+    of ``fd_substeps``).
+    """
+
+    def __init__(self, shape, storage="f32", stream=None, **kw):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        self.lib = load()
+        self.shape = tuple(int(s) for s in shape)
+        self.lattice = lattice_of(self.shape)
+        self.d = 2 if self.lattice == D2Q9 else 3
+        self.q = 9 if self.lattice == D2Q9 else 19
+        self.storage = _STORAGE[storage]
+        nx, ny, nz = _dims(self.shape)
+        self.ns = nx * ny * nz
+        nbytes = workspace_size(self.lattice, self.storage, nx, ny, nz)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._params = params(**kw)
+        ctx = _vp()
+        _check(self.lib.hlb_create(ctypes.byref(ctx), self.lattice, self.storage, nx, ny, nz,
+                                   ctypes.byref(self._params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                   nbytes, ctypes.c_void_p(self.stream.cuda_stream)))
+        self.ctx = ctx
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.hlb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- parameters
+    @property
+    def m(self) -> int:
+        m = ctypes.c_int()
+        _check(self.lib.hlb_get_params(self.ctx, None, ctypes.byref(m)), self.ctx)
+        return m.value
+
+    def set_params(self, **kw):
+        self._params = params(**kw)
+        _check(self.lib.hlb_set_params(self.ctx, ctypes.byref(self._params)), self.ctx)
+
+    # -- state
+    def init(self, phi, n=None, u=None):
+        phi = _f64(phi, self.shape)
+        n = None if n is None else _f64(n, self.shape)
+        u = None if u is None else _f64(u, (self.d,) + self.shape)
+        _check(self.lib.hlb_init_fields(self.ctx, _ptr(phi), _ptr(n), _ptr(u)), self.ctx)
+        return self
+
+    def set_state(self, f, phi):
+        f = _f64(f, (self.q,) + self.shape)
+        phi = _f64(phi, self.shape)
+        _check(self.lib.hlb_set_state(self.ctx, _ptr(f), _ptr(phi)), self.ctx)
+
+    def state(self):
+        f = np.empty((self.q,) + self.shape)
+        phi = np.empty(self.shape)
+        _check(self.lib.hlb_get_state(self.ctx, _ptr(f), _ptr(phi)), self.ctx)
+        return f, phi
+
+    # -- stepping
+    def step(self, nsteps: int = 1):
+        _check(self.lib.hlb_step(self.ctx, int(nsteps)), self.ctx)
+        return self
+
+    def step_timed(self, nsteps: int):
+        ms = (ctypes.c_double * 2)()
+        _check(self.lib.hlb_step_timed(self.ctx, int(nsteps), ms), self.ctx)
+        return float(ms[0]), float(ms[1])
+
+    def kernel_name(self, cls: int) -> str:
+        return self.lib.hlb_kernel_name(self.ctx, cls).decode()
+
+    # -- readout
+    def fields(self):
+        n = np.empty(self.shape)
+        u = np.empty((self.d,) + self.shape)
+        phi = np.empty(self.shape)
+        mu = np.empty(self.shape)
+        _check(self.lib.hlb_get_fields(self.ctx, _ptr(n), _ptr(u), _ptr(phi), _ptr(mu)), self.ctx)
+        return {"n": n, "u": u, "phi": phi, "mu": mu}
+
+    def reduce(self, raise_on_error: bool = True):
+        s = Stats()
+        status = self.lib.hlb_reduce(self.ctx, ctypes.byref(s))
+        out = {"mass": s.mass, "phi_sum": s.phi_sum, "kinetic": s.kinetic, "umax": s.umax,
+               "mom": np.array(list(s.mom)[: self.d]), "step": s.step, "finite": bool(s.finite),
+               "status": status}
+        if raise_on_error and status != HLB_OK:
+            _check(status, self.ctx)
+        return out

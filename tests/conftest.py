@@ -11,3 +11,12 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
     config.addinivalue_line("markers", "slow: long CPU run of the oracle (still part of the CPU suite)")
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Print the case name before each GPU test, so a run that ends the box
+    still names what it was doing."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print(f"\n[gpu case] {request.node.nodeid}", flush=True)
+    yield

@@ -1,0 +1,244 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Both sides start from the same seeded host arrays and are compared element
+by element.  Tolerances:
+  * FP64 storage: the two sides differ only in summation order and FMA
+    contraction, so the difference stays at a few hundred ulps of the
+    fields even after 1000 steps of a dissipative run;
+  * FP32 storage: max |dphi|, |du| <= 1e-5 after 1000 steps of the 128^2
+    drop (the target stated for this workload); shorter runs in proportion.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import orc
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(a=-0.1, b=0.1, kappa=0.1, tau=1.0, gamma=1.0)
+PAPER = dict(a=-1e-3, b=1e-3, kappa=3e-3, tau=1.0, gamma=5.0)
+OC, ISO, SC = (0.3, 2.5), (1.0 / 3.0, 2.0 / 3.0), (0.5, 1.0)
+
+
+@pytest.fixture(scope="module")
+def hlb():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0902_3921_amd import hlb as mod
+
+    mod.load()
+    return mod
+
+
+def _pair(hlb, shape, storage, phi, n=None, u=None, m=None, **kw):
+    """A GPU simulation and an oracle simulation from the same inputs."""
+    d = len(shape)
+    lattice = 0 if d == 2 else 1
+    if m is None:
+        m = hlb.check_params(lattice, **kw)
+    gpu = hlb.Sim(shape, storage, m=m, **kw)
+    gpu.init(phi, n, u)
+    ora = orc.Oracle(shape, m=m, **kw)
+    ora.init(phi, n, u)
+    return gpu, ora
+
+
+def _maxdiff(gpu, ora):
+    g, o = gpu.fields(), ora.fields()
+    return {k: float(np.abs(g[k] - o[k]).max()) for k in ("n", "u", "phi", "mu")}
+
+
+def _drop(shape, R, params):
+    a, b, kappa = params["a"], params["b"], params["kappa"]
+    return synth.drop(shape, R, np.sqrt(-a / b), np.sqrt(-2 * kappa / a))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_init_and_readout_match(hlb, storage):
+    """t = 0: f = f^eq(n0, u0) (Eq. espdistrfunc) and the readout of n, u*
+    (Eq. newvel), phi and mu (Eq. chempot)."""
+    shape = (45, 70)
+    rng = np.random.default_rng(7)
+    phi = _drop(shape, 12, BASE) + rng.uniform(-0.01, 0.01, shape)
+    n = rng.uniform(0.95, 1.05, shape)
+    u = rng.uniform(-0.01, 0.01, (2,) + shape)
+    gpu, ora = _pair(hlb, shape, storage, phi, n, u, **BASE, N=0.3, Q=2.5)
+    d = _maxdiff(gpu, ora)
+    tol = 1e-14 if storage == "f64" else 2e-7
+    assert max(d.values()) < tol, d
+    f_g, phi_g = gpu.state()
+    f_o, phi_o = ora.state()
+    assert np.abs(f_g - f_o).max() < (1e-15 if storage == "f64" else 1e-7)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_state_roundtrip(hlb, storage):
+    shape = (13, 17)
+    rng = np.random.default_rng(3)
+    w = orc.lattice(2)[1]
+    f = w[:, None, None] * rng.uniform(0.9, 1.1, (9,) + shape)
+    phi = rng.uniform(-1, 1, shape)
+    gpu = hlb.Sim(shape, storage, **BASE)
+    gpu.set_state(f, phi)
+    f2, phi2 = gpu.state()
+    # f64: f - w rho0 + w rho0 rounds once; f32: float deviations and phi
+    tol = 1e-16 if storage == "f64" else 1e-7
+    assert np.abs(f2 - f).max() < tol
+    if storage == "f64":
+        assert np.array_equal(phi2, phi)
+    else:
+        assert np.abs(phi2 - phi).max() < 1e-7
+
+
+def test_drop_128_fp64_1000_steps(hlb):
+    """The 128^2 drop (R = 20, a = -0.1, b = 0.1, kappa = 0.1, tau = 1,
+    Gamma = 1, paper stencil N = 0.3, Q = 2.5, m = 5) in FP64 storage agrees
+    with the oracle after 1000 steps."""
+    shape = (128, 128)
+    phi = _drop(shape, 20, BASE)
+    gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=0.3, Q=2.5)
+    assert gpu.m == 5
+    gpu.step(1000)
+    ora.step(1000)
+    d = _maxdiff(gpu, ora)
+    print("fp64 drop 1000 steps max diffs", d, flush=True)
+    assert d["phi"] < 1e-11 and d["u"] < 1e-12 and d["n"] < 1e-12, d
+
+
+def test_drop_128_fp32_1000_steps(hlb):
+    """Same workload with FP32 shifted populations: max |dphi|, |du| <= 1e-5."""
+    shape = (128, 128)
+    phi = _drop(shape, 20, BASE)
+    gpu, ora = _pair(hlb, shape, "f32", phi, **BASE, N=0.3, Q=2.5)
+    gpu.step(1000)
+    ora.step(1000)
+    d = _maxdiff(gpu, ora)
+    print("fp32 drop 1000 steps max diffs", d, flush=True)
+    assert d["phi"] <= 1e-5 and d["u"] <= 1e-5, d
+
+
+@pytest.mark.parametrize("stencil", [OC, ISO, SC])
+@pytest.mark.parametrize("force_form", [1, 0])
+@pytest.mark.parametrize("advection", [0, 1])
+def test_variants_fp64_ragged(hlb, stencil, force_form, advection):
+    """Every stencil preset, both force forms and both advection forms on a
+    ragged 70 x 45 lattice (not a multiple of any tile), 60 steps."""
+    shape = (45, 70)
+    phi = _drop(shape, 14, BASE)
+    u0 = np.zeros((2,) + shape)
+    u0[0] = 0.01
+    kw = dict(BASE, N=stencil[0], Q=stencil[1], force_form=force_form, advection=advection)
+    gpu, ora = _pair(hlb, shape, "f64", phi, None, u0, **kw)
+    gpu.step(60)
+    ora.step(60)
+    d = _maxdiff(gpu, ora)
+    assert max(d.values()) < 1e-12, d
+
+
+@pytest.mark.parametrize("cd_Q,m", [(1.0, 5), (2.0 / 3.0, 3), (1.0, 8)])
+def test_ch_laplacian_and_substeps(hlb, cd_Q, m):
+    shape = (40, 64)
+    phi = synth.spinodal(shape, seed=11)
+    gpu, ora = _pair(hlb, shape, "f64", phi, m=m, **BASE, N=0.3, Q=2.5, cd_Q=cd_Q)
+    gpu.step(50)
+    ora.step(50)
+    d = _maxdiff(gpu, ora)
+    assert max(d.values()) < 1e-12, d
+
+
+def test_paper_parameters_m1(hlb):
+    """The paper's parameters (-a = b = 1e-3, kappa = 3e-3, Gamma = 5), m = 1."""
+    shape = (64, 64)
+    phi = _drop(shape, 16, PAPER)
+    gpu, ora = _pair(hlb, shape, "f64", phi, **PAPER, N=0.3, Q=2.5)
+    assert gpu.m == 1
+    gpu.step(300)
+    ora.step(300)
+    d = _maxdiff(gpu, ora)
+    assert d["phi"] < 1e-14 and d["u"] < 1e-15 and d["n"] < 1e-13, d
+
+
+@pytest.mark.parametrize("storage,steps,tol", [("f64", 100, 1e-11), ("f32", 50, 1e-5)])
+def test_spinodal_short_horizon(hlb, storage, steps, tol):
+    """Spinodal decomposition from phi ~ U(-0.01, 0.01): unstable modes grow
+    roundoff, so trajectories are compared at short horizons only."""
+    shape = (64, 64)
+    phi = synth.spinodal(shape, seed=0)
+    gpu, ora = _pair(hlb, shape, storage, phi, **BASE, N=0.3, Q=2.5)
+    gpu.step(steps)
+    ora.step(steps)
+    d = _maxdiff(gpu, ora)
+    assert d["phi"] < tol and d["u"] < tol, d
+
+
+@pytest.mark.parametrize("shape", [(18, 20, 24), (7, 9, 33)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_d3q19_drop(hlb, shape, storage):
+    """D3Q19 with the 3D stencils: a drop on ragged lattices, 12 steps."""
+    phi = _drop(shape, 5, BASE)
+    u0 = np.zeros((3,) + shape)
+    u0[2] = 0.005
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=1 / 6, Q=1 / 3)
+    assert gpu.m == 10
+    gpu.step(12)
+    ora.step(12)
+    d = _maxdiff(gpu, ora)
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert max(d.values()) < tol, d
+
+
+def test_reduce_matches_oracle(hlb):
+    shape = (48, 80)
+    phi = _drop(shape, 15, BASE)
+    gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=0.3, Q=2.5)
+    gpu.step(40)
+    ora.step(40)
+    rg, ro = gpu.reduce(), ora.reduce()
+    assert rg["finite"] and ro["finite"] and rg["step"] == 40
+    for k in ("mass", "phi_sum"):
+        assert abs(rg[k] - ro[k]) < 1e-10 * abs(ro[k]) + 1e-12, k
+    assert abs(rg["kinetic"] - ro["kinetic"]) < 1e-12 * max(1.0, ro["kinetic"]) + 1e-16
+    assert abs(rg["umax"] - ro["umax"]) < 1e-13
+    np.testing.assert_allclose(rg["mom"], ro["mom"], atol=1e-12)
+
+
+def test_tiny_and_degenerate_lattices(hlb):
+    """Lattices smaller than the stencil reach (periodic images overlap)."""
+    for shape in [(1, 1), (2, 3), (5, 1), (3, 4)]:
+        rng = np.random.default_rng(sum(shape))
+        phi = rng.uniform(-0.5, 0.5, shape)
+        gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=0.3, Q=2.5)
+        gpu.step(7)
+        ora.step(7)
+        d = _maxdiff(gpu, ora)
+        assert max(d.values()) < 1e-13, (shape, d)
+
+
+def test_zero_steps_and_counter(hlb):
+    shape = (16, 16)
+    gpu = hlb.Sim(shape, "f32", **BASE)
+    gpu.init(np.zeros(shape))
+    gpu.step(0)
+    assert gpu.reduce()["step"] == 0
+    gpu.step(3)
+    assert gpu.reduce()["step"] == 3
+
+
+def test_nonfinite_state_is_reported(hlb):
+    """A state that overflows float storage is caught by the reduction, and
+    the context then refuses to step until it is re-initialised."""
+    shape = (16, 16)
+    gpu = hlb.Sim(shape, "f32", **BASE)
+    f = np.full((9,) + shape, 1e300)
+    gpu.set_state(f, np.zeros(shape))
+    r = gpu.reduce(raise_on_error=False)
+    assert r["status"] == hlb.HLB_ENONFINITE and not r["finite"]
+    with pytest.raises(hlb.HlbError) as ei:
+        gpu.step(1)
+    assert ei.value.status == hlb.HLB_ESTATE
+    gpu.init(np.zeros(shape))
+    gpu.step(1)
+    assert gpu.reduce()["finite"]
