@@ -173,8 +173,29 @@ hlb_status hlb_reduce(hlb_ctx *ctx, hlb_stats *out);
  *   kernels.  Intended for benchmarks; slower than hlb_step. */
 hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
 
+/* Execution plan of the convection-diffusion substeps (a performance
+ * choice; every plan computes the same values up to rounding order):
+ *   plan[0] kind: 0 = one tiled launch per substep (any lattice);
+ *                 1 = fused launches that march along y and run plan[1]
+ *                     substeps per pass (D2Q9 with cd_Q = 1 only);
+ *   plan[1] fuse: substeps per fused launch, 1..5;
+ *   plan[2] bw:   columns per block of the fused kernel, 64, 128 or 256
+ *                 (256 with HLB_F32_SHIFTED only), bw - 6*fuse >= 16;
+ *   plan[3] seg:  rows per block of the fused kernel, >= 1.
+ * hlb_create picks a plan from the lattice size; hlb_set_plan overrides it
+ * (HLB_EINVAL if the plan cannot run this context).  hlb_set_params keeps a
+ * user plan while it stays valid. */
+hlb_status hlb_set_plan(hlb_ctx *ctx, const int plan[4]);
+hlb_status hlb_get_plan(const hlb_ctx *ctx, int plan[4]);
+
+/* Times the candidate plans on the current state (each candidate runs the
+ * convection-diffusion kernels into the spare phi buffer, so the state is
+ * unchanged), keeps the fastest and writes its time per substep in
+ * microseconds to *best_us (may be NULL).  Synchronises. */
+hlb_status hlb_autotune(hlb_ctx *ctx, double *best_us);
+
 /* Names of the device kernels of a kernel class (0 or 1) for the context's
- * lattice and storage, as they appear in profiler traces. */
+ * lattice, storage and plan, as they appear in profiler traces. */
 const char *hlb_kernel_name(const hlb_ctx *ctx, int kernel_class);
 
 /* Message of the context's last failure ("" if none); owned by the context,

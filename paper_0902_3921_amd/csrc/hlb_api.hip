@@ -37,11 +37,11 @@ template <> struct Tiles<D2Q9, float> {
 };
 template <> struct Tiles<D3Q19, double> {
   static constexpr int LB[3] = {32, 4, 4};
-  static constexpr int CH[3] = {16, 4, 4};
+  static constexpr int CH[3] = {8, 4, 4};
 };
 template <> struct Tiles<D3Q19, float> {
   static constexpr int LB[3] = {32, 4, 4};
-  static constexpr int CH[3] = {32, 4, 4};
+  static constexpr int CH[3] = {16, 4, 4};
 };
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
@@ -210,6 +210,14 @@ hlb_status validate(int lattice, const hlb_params *p, int *m_out, std::string *m
 
 }  // namespace
 
+// Execution plan of the convection-diffusion substeps of a step.
+struct ChPlan {
+  int kind;  // 0: one tiled launch per substep; 1: fused y-march launches (D2Q9, cd_Q = 1)
+  int fuse;  // substeps per fused launch, 1..5
+  int bw;    // columns (threads) per block of the fused kernel: 64, 128 or 256
+  int seg;   // rows per block of the fused kernel
+};
+
 struct hlb_ctx {
   int lattice, storage, d, q, nx, ny, nz;
   long long ns;
@@ -225,6 +233,8 @@ struct hlb_ctx {
   bool error_state;
   std::string err;
   std::string names[2];
+  ChPlan plan;
+  bool plan_user;  // plan set through hlb_set_plan
 };
 
 namespace {
@@ -299,8 +309,44 @@ struct Ops {
                        at<T>(c, c->lay.phi[c->phicur]), at<T>(c, c->lay.u));
   }
   static void ch(hlb_ctx *c, const KParams &k) {
-    hipLaunchKernelGGL((k_ch<L, T, CH0, CH1, CH2>), tile_grid(c, TL::CH), dim3(256), 0, c->stream, k,
-                       at<T>(c, c->lay.phi[c->phicur]), at<T>(c, c->lay.u), at<T>(c, c->lay.phi[1 - c->phicur]));
+    const T *src = at<T>(c, c->lay.phi[c->phicur]);
+    T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
+    if (c->p.cd_Q == 1.0)
+      hipLaunchKernelGGL((k_ch<L, T, CH0, CH1, CH2, true>), tile_grid(c, TL::CH), dim3(256), 0, c->stream, k, src,
+                         at<T>(c, c->lay.u), dst);
+    else
+      hipLaunchKernelGGL((k_ch<L, T, CH0, CH1, CH2, false>), tile_grid(c, TL::CH), dim3(256), 0, c->stream, k, src,
+                         at<T>(c, c->lay.u), dst);
+  }
+  template <int M, int BW>
+  static void march1(hlb_ctx *c, const KParams &k, int seg, const T *src, T *dst) {
+    const dim3 grid(ceil_div(c->nx, BW - 6 * M), ceil_div(c->ny, seg));
+    if (k.advection == 1)
+      hipLaunchKernelGGL((k_ch_march<T, M, BW, true>), grid, dim3(BW), 0, c->stream, k, seg, src,
+                         at<T>(c, c->lay.u), dst);
+    else
+      hipLaunchKernelGGL((k_ch_march<T, M, BW, false>), grid, dim3(BW), 0, c->stream, k, seg, src,
+                         at<T>(c, c->lay.u), dst);
+  }
+  template <int BW>
+  static void march_bw(hlb_ctx *c, const KParams &k, int M, int seg, const T *src, T *dst) {
+    switch (M) {
+      case 1: march1<1, BW>(c, k, seg, src, dst); break;
+      case 2: march1<2, BW>(c, k, seg, src, dst); break;
+      case 3: march1<3, BW>(c, k, seg, src, dst); break;
+      case 4: march1<4, BW>(c, k, seg, src, dst); break;
+      default: march1<5, BW>(c, k, seg, src, dst); break;
+    }
+  }
+  // one fused launch of M substeps: phi[phicur] -> phi[1 - phicur]
+  static void march(hlb_ctx *c, const KParams &k, int M) {
+    if constexpr (L::D == 2) {
+      const T *src = at<T>(c, c->lay.phi[c->phicur]);
+      T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
+      if (c->plan.bw == 64) march_bw<64>(c, k, M, c->plan.seg, src, dst);
+      else if (c->plan.bw == 128) march_bw<128>(c, k, M, c->plan.seg, src, dst);
+      else if constexpr (sizeof(T) == 4) march_bw<256>(c, k, M, c->plan.seg, src, dst);
+    }
   }
   static void init(hlb_ctx *c, const KParams &k) {
     const unsigned nb = (unsigned)((c->ns + 255) / 256);
@@ -375,14 +421,73 @@ void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], c->stream);
     ops.lb(c, k);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
-    for (int s = 0; s < c->m; s++) {
-      ops.ch(c, k);
-      c->phicur = 1 - c->phicur;
+    if (c->plan.kind == 1) {
+      // substeps fused c->plan.fuse at a time, each launch with dt = 1/m
+      for (int done = 0; done < c->m;) {
+        const int M = std::min(c->plan.fuse, c->m - done);
+        ops.march(c, k, M);
+        c->phicur = 1 - c->phicur;
+        done += M;
+      }
+    } else {
+      for (int s = 0; s < c->m; s++) {
+        ops.ch(c, k);
+        c->phicur = 1 - c->phicur;
+      }
     }
     if (ev) (void)hipEventRecord(ev[2], c->stream);
   });
   c->gcur = 1 - c->gcur;
   c->step++;
+}
+
+// Whether a plan can run this context.
+bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
+  if (pl.kind == 0) return true;
+  if (pl.kind != 1) {
+    *why = "plan kind must be 0 or 1";
+    return false;
+  }
+  if (c->lattice != HLB_D2Q9 || c->p.cd_Q != 1.0) {
+    *why = "the fused substep kernel needs D2Q9 and cd_Q = 1";
+    return false;
+  }
+  if (pl.fuse < 1 || pl.fuse > 5) {
+    *why = "fuse must be in 1..5";
+    return false;
+  }
+  if (pl.bw != 64 && pl.bw != 128 && pl.bw != 256) {
+    *why = "bw must be 64, 128 or 256";
+    return false;
+  }
+  if (pl.bw == 256 && c->storage == HLB_F64) {
+    *why = "bw = 256 needs float storage (LDS size)";
+    return false;
+  }
+  if (pl.bw - 6 * pl.fuse < 16) {
+    *why = "bw - 6 fuse must be >= 16";
+    return false;
+  }
+  if (pl.seg < 1) {
+    *why = "seg must be >= 1";
+    return false;
+  }
+  return true;
+}
+
+ChPlan default_plan(const hlb_ctx *c) {
+  ChPlan pl{0, 1, 128, 64};
+  if (c->lattice != HLB_D2Q9 || c->p.cd_Q != 1.0) return pl;
+  pl.kind = 1;
+  pl.fuse = std::min(c->m, 5);
+  pl.bw = pl.fuse <= 2 ? 64 : 128;
+  if (c->storage == HLB_F32_SHIFTED && c->ns >= (4LL << 20) && pl.fuse >= 3) pl.bw = 256;
+  // rows per block: enough blocks to give every CU several, at least 16 rows
+  const int out_w = pl.bw - 6 * pl.fuse;
+  const long long strips = ceil_div(c->nx, out_w);
+  long long seg = (long long)c->ny * strips / 2048;
+  pl.seg = (int)std::max(16LL, std::min<long long>(seg, 256));
+  return pl;
 }
 
 std::string kernel_names(int lattice, int storage, int cls) {
@@ -476,6 +581,8 @@ hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, i
   c->error_state = false;
   c->names[0] = kernel_names(lattice, storage, 0);
   c->names[1] = kernel_names(lattice, storage, 1);
+  c->plan = default_plan(c);
+  c->plan_user = false;
   *out = c;
   return HLB_OK;
 }
@@ -488,6 +595,11 @@ hlb_status hlb_set_params(hlb_ctx *c, const hlb_params *p) {
   if (s != HLB_OK) return fail(c, s, msg);
   c->p = *p;
   c->m = m;
+  std::string why;
+  if (!c->plan_user || !plan_valid(c, c->plan, &why)) {
+    c->plan = default_plan(c);
+    c->plan_user = false;
+  }
   return HLB_OK;
 }
 
@@ -681,7 +793,91 @@ hlb_status hlb_reduce(hlb_ctx *c, hlb_stats *out) {
 
 const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
   if (!c || cls < 0 || cls > 1) return "";
+  if (cls == 1 && c->plan.kind == 1) {
+    hlb_ctx *mc = const_cast<hlb_ctx *>(c);
+    char buf[160];
+    snprintf(buf, sizeof buf, "hlb::k_ch_march<%s, %d, %d>", c->storage == HLB_F64 ? "double" : "float",
+             std::min(c->plan.fuse, c->m), c->plan.bw);
+    mc->names[1] = buf;
+  } else if (cls == 1) {
+    const_cast<hlb_ctx *>(c)->names[1] = kernel_names(c->lattice, c->storage, 1);
+  }
   return c->names[cls].c_str();
+}
+
+hlb_status hlb_set_plan(hlb_ctx *c, const int plan[4]) {
+  if (!c || !plan) return HLB_EINVAL;
+  ChPlan pl{plan[0], plan[1], plan[2], plan[3]};
+  std::string why;
+  if (!plan_valid(c, pl, &why)) return fail(c, HLB_EINVAL, why);
+  c->plan = pl;
+  c->plan_user = true;
+  return HLB_OK;
+}
+
+hlb_status hlb_get_plan(const hlb_ctx *c, int plan[4]) {
+  if (!c || !plan) return HLB_EINVAL;
+  plan[0] = c->plan.kind;
+  plan[1] = c->plan.fuse;
+  plan[2] = c->plan.bw;
+  plan[3] = c->plan.seg;
+  return HLB_OK;
+}
+
+hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
+  hlb_status s = usable(c);
+  if (s != HLB_OK) return s;
+  // candidate plans, each timed on the convection-diffusion launch that reads
+  // the current phi and writes the spare buffer, so the state is unchanged
+  std::vector<ChPlan> cand;
+  cand.push_back(ChPlan{0, 1, 128, 64});
+  if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
+    const int fuse = std::min(c->m, 5);
+    for (int bw : {64, 128, 256})
+      for (int seg : {8, 16, 32, 64, 128, 256}) {
+        ChPlan pl{1, fuse, bw, seg};
+        std::string why;
+        if (plan_valid(c, pl, &why)) cand.push_back(pl);
+      }
+  }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return fail(c, HLB_EHIP, "hipEventCreate");
+  const KParams k = kparams(c);
+  const ChPlan saved = c->plan;
+  double best = 1e300;
+  ChPlan best_pl = saved;
+  for (const ChPlan &pl : cand) {
+    c->plan = pl;
+    const int per = pl.kind == 1 ? std::min(pl.fuse, c->m) : 1;  // substeps per timed launch
+    float ms = 0;
+    for (int rep = 0; rep < 4; rep++) {
+      (void)hipEventRecord(e0, c->stream);
+      dispatch(c, [&](auto ops) {
+        if (pl.kind == 1) ops.march(c, k, per);
+        else ops.ch(c, k);
+      });
+      (void)hipEventRecord(e1, c->stream);
+      s = launch_check(c, "autotune launch");
+      if (s == HLB_OK) s = sync(c);
+      if (s != HLB_OK) break;
+      float t = 0;
+      (void)hipEventElapsedTime(&t, e0, e1);
+      if (rep > 0) ms += t;  // first launch warms up
+    }
+    if (s != HLB_OK) break;
+    const double us_per_substep = ms / 3.0 * 1e3 / per;
+    if (us_per_substep < best) {
+      best = us_per_substep;
+      best_pl = pl;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->plan = s == HLB_OK ? best_pl : saved;
+  c->plan_user = s == HLB_OK;
+  if (best_us) *best_us = best;
+  return s;
 }
 
 const char *hlb_last_error(const hlb_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }

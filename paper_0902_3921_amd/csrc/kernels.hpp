@@ -90,15 +90,91 @@ __device__ __forceinline__ void grad_at(const T (&s)[PZ][PY][PX], int x, int y, 
 }
 
 // Stage field[] over the box starting at global (gx0, gy0, gz0) (periodic
-// wrap) into an LDS tile.
+// wrap) into an LDS tile.  When the lattice is at least as large as the box
+// on every axis a single conditional wrap is exact; smaller lattices (tiles
+// that wrap more than once) take the modulo path.  The branch is uniform.
+__device__ __forceinline__ int wrap1(int v, int n) {
+  v += v < 0 ? n : 0;
+  return v >= n ? v - n : v;
+}
+
+// Threads per block of every stencil kernel.
+constexpr int NT = 256;
+
+// Global -> LDS staging in two halves: issue() puts all of a thread's loads
+// in flight into registers, commit() writes them to LDS.  Issuing every load
+// of a kernel (tiles and populations) before the first use keeps the memory
+// pipeline full instead of paying one latency per loop iteration.
+template <int D, typename T, int PX, int PY, int PZ>
+struct TileLoad {
+  static constexpr int N = PX * PY * PZ;
+  static constexpr int K = (N + NT - 1) / NT;
+  T v[K];
+
+  __device__ __forceinline__ void issue(const T *__restrict__ field, const KParams &p, int gx0, int gy0, int gz0) {
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const bool inside = gx0 >= 0 && gx0 + PX <= nx && gy0 >= 0 && gy0 + PY <= ny &&
+                        (D == 2 || (gz0 >= 0 && gz0 + PZ <= nz));
+    if (inside) {  // no periodic image involved
+      const T *base = field + gx0 + nx * (gy0 + ny * (D == 3 ? gz0 : 0));
+#pragma unroll
+      for (int k = 0; k < K; k++) {
+        const int i = threadIdx.x + k * NT;
+        if (N % NT == 0 || i < N) {
+          const int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
+          v[k] = base[lx + nx * (ly + ny * lz)];
+        }
+      }
+      return;
+    }
+    const bool fast = nx >= PX && ny >= PY && (D == 2 || nz >= PZ);
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NT;
+      if (N % NT == 0 || i < N) {
+        const int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
+        int gx, gy, gz = 0;
+        if (fast) {
+          gx = wrap1(gx0 + lx, nx);
+          gy = wrap1(gy0 + ly, ny);
+          if (D == 3) gz = wrap1(gz0 + lz, nz);
+        } else {
+          gx = wrapc(gx0 + lx, nx);
+          gy = wrapc(gy0 + ly, ny);
+          if (D == 3) gz = wrapc(gz0 + lz, nz);
+        }
+        v[k] = field[gx + nx * (gy + ny * gz)];
+      }
+    }
+  }
+
+  __device__ __forceinline__ void commit(T (&s)[PZ][PY][PX]) const {
+    T *flat = &s[0][0][0];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NT;
+      if (N % NT == 0 || i < N) flat[i] = v[k];
+    }
+  }
+};
+
 template <int D, typename T, int PX, int PY, int PZ>
 __device__ __forceinline__ void load_tile(T (&s)[PZ][PY][PX], const T *__restrict__ field, const KParams &p,
                                           int gx0, int gy0, int gz0) {
-  for (int i = threadIdx.x; i < PX * PY * PZ; i += blockDim.x) {
-    const int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
-    const int gx = wrapc(gx0 + lx, p.nx), gy = wrapc(gy0 + ly, p.ny);
-    const int gz = (D == 3) ? wrapc(gz0 + lz, p.nz) : 0;
-    s[lz][ly][lx] = field[gx + p.nx * (gy + p.ny * gz)];
+  TileLoad<D, T, PX, PY, PZ> t;
+  t.issue(field, p, gx0, gy0, gz0);
+  t.commit(s);
+}
+
+// Laplacian with R = 0 (the standard 5/7-point operator): axis neighbours only.
+template <int D, typename T, int PX, int PY, int PZ>
+__device__ __forceinline__ T lap5_at(const T (&s)[PZ][PY][PX], int x, int y, int z, T Q, T C) {
+  if constexpr (D == 2) {
+    return Q * ((s[0][y][x + 1] + s[0][y][x - 1]) + (s[0][y + 1][x] + s[0][y - 1][x])) + C * s[0][y][x];
+  } else {
+    return Q * ((s[z][y][x + 1] + s[z][y][x - 1]) + (s[z][y + 1][x] + s[z][y - 1][x]) +
+                (s[z + 1][y][x] + s[z - 1][y][x])) +
+           C * s[z][y][x];
   }
 }
 
@@ -113,13 +189,21 @@ struct ForceTile {
   T phi[PZ][PY][PX];
   T lam[LZ][LY][LX];  // lap_D phi (expanded form) or mu (mu-first form)
 
-  __device__ __forceinline__ void build(const T *__restrict__ gphi, const KParams &p, int x0, int y0, int z0) {
-    load_tile<D>(phi, gphi, p, x0 - H, y0 - H, D == 3 ? z0 - H : 0);
+  using Loader = TileLoad<D, T, PX, PY, PZ>;
+
+  __device__ __forceinline__ void issue(Loader &ld, const T *__restrict__ gphi, const KParams &p, int x0, int y0,
+                                        int z0) const {
+    ld.issue(gphi, p, x0 - H, y0 - H, D == 3 ? z0 - H : 0);
+  }
+
+  // Commit phi to LDS and form lap_D phi (or mu) on the tile plus a halo of 1.
+  __device__ __forceinline__ void finish(const Loader &ld, const KParams &p) {
+    ld.commit(phi);
     __syncthreads();
     const T Q = T(p.lQ), R = T(p.lR), C = T(p.lC);
     const T a = T(p.a), b = T(p.b), kappa = T(p.kappa);
     const bool mu_first = p.force_form == 0;
-    for (int i = threadIdx.x; i < LX * LY * LZ; i += blockDim.x) {
+    for (int i = threadIdx.x; i < LX * LY * LZ; i += NT) {
       const int lx = i % LX, ly = (i / LX) % LY, lz = i / (LX * LY);
       const int px = lx + 1, py = ly + 1, pz = D == 3 ? lz + 1 : 0;
       const T l = lap_at<D>(phi, px, py, pz, Q, R, C);
@@ -131,6 +215,12 @@ struct ForceTile {
       }
     }
     __syncthreads();
+  }
+
+  __device__ __forceinline__ void build(const T *__restrict__ gphi, const KParams &p, int x0, int y0, int z0) {
+    Loader ld;
+    issue(ld, gphi, p, x0, y0, z0);
+    finish(ld, p);
   }
 
   // Force density at tile site (tx, ty, tz), without the body-force term;
@@ -159,17 +249,15 @@ struct ForceTile {
   }
 };
 
-// Pull the pre-collision populations of site (x, y, z) (g_i from r - e_i,
-// periodic) and form the moments: dn = sum g_i (n = rho0 + dn), j = sum g_i e_i.
+// Pull the pre-collision populations of site (x, y, z): g_i from r - e_i
+// (periodic).  Loads only; moments() forms the sums.
 template <class L, typename T>
-__device__ __forceinline__ void pull(const KParams &p, const T *__restrict__ g, int x, int y, int z, T f[L::Q],
-                                     T &dn, T j[3]) {
+__device__ __forceinline__ void pull_issue(const KParams &p, const T *__restrict__ g, int x, int y, int z,
+                                           T f[L::Q]) {
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int xs[3] = {x == 0 ? nx - 1 : x - 1, x, x == nx - 1 ? 0 : x + 1};
   const int ys[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
   const int zs[3] = {z == 0 ? nz - 1 : z - 1, z, z == nz - 1 ? 0 : z + 1};
-  dn = T(0);
-  j[0] = j[1] = j[2] = T(0);
   const size_t ns = (size_t)p.ns;
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
@@ -181,7 +269,13 @@ __device__ __forceinline__ void pull(const KParams &p, const T *__restrict__ g, 
       src = xs[1 - ex] + nx * (ys[1 - ey] + ny * zs[1 - ez]);
     f[i] = g[(size_t)i * ns + src];
   }
-  // sums in a fixed order, independent of the load schedule
+}
+
+// dn = sum g_i (n = rho0 + dn) and j = sum g_i e_i, in a fixed order.
+template <class L, typename T>
+__device__ __forceinline__ void moments(const T f[L::Q], T &dn, T j[3]) {
+  dn = T(0);
+  j[0] = j[1] = j[2] = T(0);
 #pragma unroll
   for (int i = 0; i < L::Q; i++) {
     dn += f[i];
@@ -194,56 +288,104 @@ __device__ __forceinline__ void pull(const KParams &p, const T *__restrict__ g, 
   }
 }
 
+template <class L, typename T>
+__device__ __forceinline__ void pull(const KParams &p, const T *__restrict__ g, int x, int y, int z, T f[L::Q],
+                                     T &dn, T j[3]) {
+  pull_issue<L>(p, g, x, y, z, f);
+  moments<L>(f, dn, j);
+}
+
+// Forced BGK collision of one site, written to the post-collision store.
+// With f^eq of Eq. espdistrfunc at u* and the forcing term of
+// Eq. latticeforceterm, post_i = (1 - w) f_i + w f_i^eq + F_i (w = 1/tau)
+// splits, for a velocity and its opposite, into a part even in e_i and a
+// part odd in e_i:
+//   post_{+-} = (1 - omega) g_{+-} + w_i [A + eu (B eu + C eF)] +- w_i [D eu + E eF]
+// with eu = e_i.u*, eF = e_i.F and the site constants
+//   A = omega (dn - 3/2 n u.u) - 3 (1 - omega/2) u.F,  B = 9/2 omega n,
+//   C = 9 (1 - omega/2),  D = 3 omega n,  E = 3 (1 - omega/2),
+// so each pair costs one evaluation.  Populations are deviations
+// g = f - w rho0 (dn = n - rho0).
+template <class L, typename T>
+__device__ __forceinline__ void collide(const T f[L::Q], T dn, T n, const T u[3], const T F[3], T omega, T fac,
+                                        T *__restrict__ gout, size_t ns, int idx) {
+  constexpr int D = L::D;
+  const T usq = u[0] * u[0] + u[1] * u[1] + (D == 3 ? u[2] * u[2] : T(0));
+  const T uF = u[0] * F[0] + u[1] * F[1] + (D == 3 ? u[2] * F[2] : T(0));
+  const T om1 = T(1) - omega;
+  const T A = omega * (dn - T(1.5) * n * usq) - T(3) * fac * uF;
+  const T B = T(4.5) * omega * n, C = T(9) * fac, Dc = T(3) * omega * n, E = T(3) * fac;
+  gout[idx] = om1 * f[0] + T(L::w(0)) * A;
+#pragma unroll
+  for (int i = 1; i < L::Q; i++) {
+    const int o = L::opp(i);
+    if (o < i) continue;
+    const int ex = L::e(i, 0), ey = L::e(i, 1), ez = L::e(i, 2);
+    const T eu = T(ex) * u[0] + T(ey) * u[1] + (D == 3 ? T(ez) * u[2] : T(0));
+    const T eF = T(ex) * F[0] + T(ey) * F[1] + (D == 3 ? T(ez) * F[2] : T(0));
+    const T w = T(L::w(i));
+    const T sym = w * (A + eu * (B * eu + C * eF));
+    const T asym = w * (Dc * eu + E * eF);
+    gout[(size_t)i * ns + idx] = om1 * f[i] + (sym + asym);
+    gout[(size_t)o * ns + idx] = om1 * f[o] + (sym - asym);
+  }
+}
+
 // ------------------------------------------------------------------ kernels
 // Force (Eq. forza) + moments (Eq. newvel) + forced BGK collision
 // (Eqs. espdistrfunc, forceevoleqn, latticeforceterm) + streaming.
 // Writes the post-collision populations of time t at r (pull storage) and u*_t.
 template <class L, typename T, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256) k_lb(KParams p, const T *__restrict__ gin, T *__restrict__ gout,
-                                            const T *__restrict__ phi, T *__restrict__ uout) {
+__global__ void __launch_bounds__(NT) k_lb(KParams p, const T *__restrict__ gin, T *__restrict__ gout,
+                                           const T *__restrict__ phi, T *__restrict__ uout) {
   constexpr int D = L::D;
-  __shared__ ForceTile<D, T, TX, TY, TZ> tile;
+  constexpr int NSITE = (TX * TY * TZ + NT - 1) / NT;  // sites per thread
+  using FT = ForceTile<D, T, TX, TY, TZ>;
+  __shared__ FT tile;
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * TZ : 0;
-  tile.build(phi, p, x0, y0, z0);
+
+  // all global loads first: this thread's populations, then the phi tile
+  T f[NSITE][L::Q];
+  int sx[NSITE], sy[NSITE], sz[NSITE];
+  bool ok[NSITE];
+#pragma unroll
+  for (int k = 0; k < NSITE; k++) {
+    const int s = threadIdx.x + k * NT;
+    const int tx = s % TX, ty = (s / TX) % TY, tz = s / (TX * TY);
+    sx[k] = tx;
+    sy[k] = ty;
+    sz[k] = tz;
+    ok[k] = s < TX * TY * TZ && x0 + tx < p.nx && y0 + ty < p.ny && z0 + tz < p.nz;
+    if (ok[k]) pull_issue<L>(p, gin, x0 + tx, y0 + ty, z0 + tz, f[k]);
+  }
+  typename FT::Loader ld;
+  tile.issue(ld, phi, p, x0, y0, z0);
+  tile.finish(ld, p);
 
   const T rho0 = T(p.rho0), omega = T(p.omega);
   const T fac = T(1) - T(0.5) * omega;  // 1 - 1/(2 tau)
   const size_t ns = (size_t)p.ns;
-  for (int s = threadIdx.x; s < TX * TY * TZ; s += blockDim.x) {
-    const int tx = s % TX, ty = (s / TX) % TY, tz = s / (TX * TY);
-    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
-    if (x >= p.nx || y >= p.ny || z >= p.nz) continue;
-    const int idx = x + p.nx * (y + p.ny * z);
-
+#pragma unroll
+  for (int k = 0; k < NSITE; k++) {
+    if (!ok[k]) continue;
+    const int tx = sx[k], ty = sy[k], tz = sz[k];
+    const int idx = (x0 + tx) + p.nx * ((y0 + ty) + p.ny * (z0 + tz));
     T F[3], ph, mu;
     tile.force(p, tx, ty, tz, F, ph, mu);
-    T f[L::Q], dn, j[3];
-    pull<L>(p, gin, x, y, z, f, dn, j);
+    T dn, j[3];
+    moments<L>(f[k], dn, j);
     const T n = rho0 + dn;
     T u[3];
     const T inv_n = T(1) / n;
 #pragma unroll
-    for (int k = 0; k < 3; k++) {
-      F[k] += n * T(p.g[k]);
-      u[k] = (j[k] + T(0.5) * F[k]) * inv_n;
+    for (int c = 0; c < 3; c++) {
+      F[c] += n * T(p.g[c]);
+      u[c] = (j[c] + T(0.5) * F[c]) * inv_n;
     }
 #pragma unroll
-    for (int k = 0; k < D; k++) uout[k * ns + idx] = u[k];
+    for (int c = 0; c < D; c++) uout[c * ns + idx] = u[c];
 
-    const T usq = u[0] * u[0] + u[1] * u[1] + (D == 3 ? u[2] * u[2] : T(0));
-    const T uF = u[0] * F[0] + u[1] * F[1] + (D == 3 ? u[2] * F[2] : T(0));
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-      const int ex = L::e(i, 0), ey = L::e(i, 1), ez = L::e(i, 2);
-      const T eu = T(ex) * u[0] + T(ey) * u[1] + (D == 3 ? T(ez) * u[2] : T(0));
-      const T eF = T(ex) * F[0] + T(ey) * F[1] + (D == 3 ? T(ez) * F[2] : T(0));
-      const T w = T(L::w(i));
-      // g^eq = f^eq - w rho0 = w [dn + n (3 e.u + 9/2 (e.u)^2 - 3/2 u.u)]
-      const T geq = w * (dn + n * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * usq));
-      // lattice forcing term, (1 - 1/2tau) w [3 (e - u).F + 9 (e.u)(e.F)]
-      const T S = fac * w * (T(3) * (eF - uF) + T(9) * eu * eF);
-      gout[(size_t)i * ns + idx] = f[i] - omega * (f[i] - geq) + S;
-    }
+    collide<L>(f[k], dn, n, u, F, omega, fac, gout, ns, idx);
   }
 }
 
@@ -251,9 +393,11 @@ __global__ void __launch_bounds__(256) k_lb(KParams p, const T *__restrict__ gin
 // h = phi - dt [phi div_c u + u . D^up phi] (Eqs. adv, centrdiff, backdiff,
 // fordiff; or the flux form), then phi' = h + dt Gamma L[a h + b phi^3 - kappa L h],
 // which equals Eq. diff, h + dt Gamma [a L h + b L phi^3 - kappa L L h], by
-// linearity of L.
-template <class L, typename T, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(256) k_ch(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
+// linearity of L.  phi and u* are staged with a halo of 3, h is formed on the
+// tile plus a halo of 2 and the diffusion potential on the tile plus 1, all
+// in LDS.  LAP5: the Laplacian has no edge weights (cd_Q = 1).
+template <class L, typename T, int TX, int TY, int TZ, bool LAP5>
+__global__ void __launch_bounds__(NT) k_ch(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
                                             T *__restrict__ phi_out) {
   constexpr int D = L::D;
   constexpr int H = 3;
@@ -261,50 +405,36 @@ __global__ void __launch_bounds__(256) k_ch(KParams p, const T *__restrict__ phi
   constexpr int HX = TX + 4, HY = TY + 4, HZ = D == 3 ? TZ + 4 : 1;
   constexpr int MX = TX + 2, MY = TY + 2, MZ = D == 3 ? TZ + 2 : 1;
   __shared__ T sphi[PZ][PY][PX];
+  __shared__ T su[D][PZ][PY][PX];
   __shared__ T sh[HZ][HY][HX];
   __shared__ T smu[MZ][MY][MX];
   const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * TZ : 0;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const size_t ns = (size_t)p.ns;
-  load_tile<D>(sphi, phi_in, p, x0 - H, y0 - H, D == 3 ? z0 - H : 0);
+  {
+    TileLoad<D, T, PX, PY, PZ> lphi, lu[D];
+    lphi.issue(phi_in, p, x0 - H, y0 - H, D == 3 ? z0 - H : 0);
+#pragma unroll
+    for (int a = 0; a < D; a++) lu[a].issue(u + a * ns, p, x0 - H, y0 - H, D == 3 ? z0 - H : 0);
+    lphi.commit(sphi);
+#pragma unroll
+    for (int a = 0; a < D; a++) lu[a].commit(su[a]);
+  }
   __syncthreads();
 
   const T dt = T(p.dt);
   const bool flux = p.advection == 1;
   // advection half-step on the tile plus a halo of 2
-  for (int i = threadIdx.x; i < HX * HY * HZ; i += blockDim.x) {
+  for (int i = threadIdx.x; i < HX * HY * HZ; i += NT) {
     const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
     const int px = hx + 1, py = hy + 1, pz = D == 3 ? hz + 1 : 0;
-    const int gx = wrapc(x0 - 2 + hx, nx), gy = wrapc(y0 - 2 + hy, ny);
-    const int gz = D == 3 ? wrapc(z0 - 2 + hz, nz) : 0;
-    const int gxm = gx == 0 ? nx - 1 : gx - 1, gxp = gx == nx - 1 ? 0 : gx + 1;
-    const int gym = gy == 0 ? ny - 1 : gy - 1, gyp = gy == ny - 1 ? 0 : gy + 1;
-    const int gzm = gz == 0 ? nz - 1 : gz - 1, gzp = gz == nz - 1 ? 0 : gz + 1;
-    const int c = gx + nx * (gy + ny * gz);
     const T ph = sphi[pz][py][px];
     T rhs = T(0);
 #pragma unroll
     for (int a = 0; a < D; a++) {
-      int im, ip;
-      T pm, pp;
-      if (a == 0) {
-        im = gxm + nx * (gy + ny * gz);
-        ip = gxp + nx * (gy + ny * gz);
-        pm = sphi[pz][py][px - 1];
-        pp = sphi[pz][py][px + 1];
-      } else if (a == 1) {
-        im = gx + nx * (gym + ny * gz);
-        ip = gx + nx * (gyp + ny * gz);
-        pm = sphi[pz][py - 1][px];
-        pp = sphi[pz][py + 1][px];
-      } else {
-        im = gx + nx * (gy + ny * gzm);
-        ip = gx + nx * (gy + ny * gzp);
-        pm = sphi[pz - 1][py][px];
-        pp = sphi[pz + 1][py][px];
-      }
-      const T *ua = u + a * ns;
-      const T uc = ua[c], um = ua[im], up = ua[ip];
+      const int ox = a == 0, oy = a == 1, oz = a == 2;
+      const T pm = sphi[pz - oz][py - oy][px - ox], pp = sphi[pz + oz][py + oy][px + ox];
+      const T um = su[a][pz - oz][py - oy][px - ox], uc = su[a][pz][py][px], up = su[a][pz + oz][py + oy][px + ox];
       if (!flux) {
         const T dcu = (up - um) * T(0.5);
         const T dup = uc > T(0) ? ph - pm : pp - ph;
@@ -323,13 +453,14 @@ __global__ void __launch_bounds__(256) k_ch(KParams p, const T *__restrict__ phi
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa);
   const T cQ = T(p.cQ), cR = T(p.cR), cC = T(p.cC);
   // diffusion potential a h + b phi^3 - kappa L h on the tile plus a halo of 1
-  for (int i = threadIdx.x; i < MX * MY * MZ; i += blockDim.x) {
+  for (int i = threadIdx.x; i < MX * MY * MZ; i += NT) {
     const int mx = i % MX, my = (i / MX) % MY, mz = i / (MX * MY);
     const int hx = mx + 1, hy = my + 1, hz = D == 3 ? mz + 1 : 0;
     const int px = mx + 2, py = my + 2, pz = D == 3 ? mz + 2 : 0;
     const T ph = sphi[pz][py][px];
     const T h = sh[hz][hy][hx];
-    smu[mz][my][mx] = a * h + b * ph * ph * ph - kappa * lap_at<D>(sh, hx, hy, hz, cQ, cR, cC);
+    const T Lh = LAP5 ? lap5_at<D>(sh, hx, hy, hz, cQ, cC) : lap_at<D>(sh, hx, hy, hz, cQ, cR, cC);
+    smu[mz][my][mx] = a * h + b * ph * ph * ph - kappa * Lh;
   }
   __syncthreads();
 
@@ -340,7 +471,136 @@ __global__ void __launch_bounds__(256) k_ch(KParams p, const T *__restrict__ phi
     if (x >= nx || y >= ny || z >= nz) continue;
     const int mx = tx + 1, my = ty + 1, mz = D == 3 ? tz + 1 : 0;
     const int hx = tx + 2, hy = ty + 2, hz = D == 3 ? tz + 2 : 0;
-    phi_out[x + nx * (y + ny * z)] = sh[hz][hy][hx] + dtg * lap_at<D>(smu, mx, my, mz, cQ, cR, cC);
+    const T Lmu = LAP5 ? lap5_at<D>(smu, mx, my, mz, cQ, cC) : lap_at<D>(smu, mx, my, mz, cQ, cR, cC);
+    phi_out[x + nx * (y + ny * z)] = sh[hz][hy][hx] + dtg * Lmu;
+  }
+}
+
+// M convection-diffusion substeps in one pass (2D, standard 5-point
+// Laplacian).  A block of BW threads owns BW consecutive lattice columns
+// (one per thread) and marches along y.  Substep s runs 3 rows behind
+// substep s-1, because one substep of Sec. 2.3 reads phi three rows away
+// (advection 1 + the two Laplacians of Eq. diff); its output row is the next
+// input row of substep s+1, in a register of the same thread.  Each thread
+// keeps, per substep, the last three rows of phi^s, h and the diffusion
+// potential of its column in registers (the y neighbours); the x neighbours
+// come from one LDS row per quantity that every thread publishes at the
+// start of an iteration, and u* from an LDS ring of its last 3M+1 rows.  One
+// barrier per row.  Output columns: the middle BW - 6M; output rows: the
+// segment [y0, y1) of the block; the march starts 3M rows before y0 and
+// ends 3M rows after y1 - 1.  phi and u* are read once and phi' written once
+// per site for all M substeps.
+template <typename T, int M, int BW, bool FLUX>
+__global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__restrict__ phi_in,
+                                                 const T *__restrict__ u, T *__restrict__ phi_out) {
+  constexpr int R = 3 * M + 1;  // rows of the u* ring
+  constexpr int PF = 1;         // rows loaded ahead of use
+  __shared__ T xphi[2][M][BW], xh[2][M][BW], xmu[2][M][BW];
+  __shared__ T sux[R][BW], suy[R][BW];
+  const int nx = p.nx, ny = p.ny;
+  const int c = threadIdx.x;
+  const int X0 = blockIdx.x * (BW - 6 * M);
+  const int y0 = blockIdx.y * seg, y1 = min(y0 + seg, ny);
+  const int gx = wrapc(X0 - 3 * M + c, nx);
+  const bool col_out = c >= 3 * M && c < BW - 3 * M && X0 + c - 3 * M < nx;
+  const int cm = c > 0 ? c - 1 : 0, cp = c < BW - 1 ? c + 1 : BW - 1;  // edge lanes: values unused
+  const size_t ns = (size_t)p.ns;
+  const T *ux_g = u, *uy_g = u + ns;
+  const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
+  const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
+  const bool wide = ny >= 3 * M + PF;  // rows wrap at most once
+
+  // per substep: phi rows (t-3s-2, t-3s-1), h rows (t-3s-3, t-3s-2), mu rows (t-3s-4, t-3s-3)
+  T ph2[M], ph1[M], h2[M], h1[M], m2[M], m1[M];
+#pragma unroll
+  for (int s = 0; s < M; s++) ph2[s] = ph1[s] = h2[s] = h1[s] = m2[s] = m1[s] = T(0);
+
+  const int t0 = y0 - 3 * M, t1 = y1 + 3 * M;  // iterations [t0, t1)
+  auto row_of = [&](int t) { return wide ? wrap1(t, ny) : wrapc(t, ny); };
+  // input rows t .. t + PF - 1 in flight, slot (t - t0) % PF
+  T qphi[PF], qux[PF], quy[PF];
+#pragma unroll
+  for (int k = 0; k < PF; k++) {
+    qphi[k] = qux[k] = quy[k] = T(0);
+    if (t0 + k < t1) {
+      const int g = gx + nx * row_of(t0 + k);
+      qphi[k] = phi_in[g];
+      qux[k] = ux_g[g];
+      quy[k] = uy_g[g];
+    }
+  }
+
+  auto iterate = [&](int t, T &rphi, T &rux, T &ruy) {
+    const int par = t & 1;
+    const int slot = (t - t0) % R;
+    // publish last iteration's rows and the new u* row
+    sux[slot][c] = rux;
+    suy[slot][c] = ruy;
+#pragma unroll
+    for (int s = 0; s < M; s++) {
+      xphi[par][s][c] = ph1[s];
+      xh[par][s][c] = h1[s];
+      xmu[par][s][c] = m1[s];
+    }
+    T in = rphi;  // phi^0 row t
+    if (t + PF < t1) {  // refill this queue slot with row t + PF
+      const int g = gx + nx * row_of(t + PF);
+      rphi = phi_in[g];
+      rux = ux_g[g];
+      ruy = uy_g[g];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < M; s++) {
+      // u* rows t-3s-2 (below), t-3s-1 (centre), t-3s (above) of the ring
+      int kc = (t - t0 - 3 * s - 1) % R;
+      kc += kc < 0 ? R : 0;
+      const int kd = kc == 0 ? R - 1 : kc - 1, ku = kc == R - 1 ? 0 : kc + 1;
+      // advection half-step at row t-3s-1
+      const T pc = ph1[s], pdn = ph2[s], pup = in;
+      const T pw = xphi[par][s][cm], pe = xphi[par][s][cp];
+      const T uxc = sux[kc][c], uxw = sux[kc][cm], uxe = sux[kc][cp];
+      const T uyc = suy[kc][c], uyd = suy[kd][c], uyu = suy[ku][c];
+      T rhs;
+      if constexpr (!FLUX) {
+        const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
+        const T ty = pc * ((uyu - uyd) * T(0.5)) + uyc * (uyc > T(0) ? pc - pdn : pup - pc);
+        rhs = tx + ty;
+      } else {
+        const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
+        const T vyu = (uyc + uyu) * T(0.5), vyd = (uyd + uyc) * T(0.5);
+        const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
+        const T ty = (vyu > T(0) ? vyu * pc : vyu * pup) - (vyd > T(0) ? vyd * pdn : vyd * pc);
+        rhs = tx + ty;
+      }
+      const T hn = pc - dt * rhs;
+      // diffusion potential at row t-3s-2: a h + b phi^3 - kappa L h
+      const T hc = h1[s];
+      const T Lh = cQ * ((xh[par][s][cp] + xh[par][s][cm]) + (hn + h2[s])) + cC * hc;
+      const T ps = ph2[s];
+      const T mn = a * hc + b * ps * ps * ps - kappa * Lh;
+      // phi^{s+1} at row t-3s-3: h + dt Gamma L mu
+      const T mc = m1[s];
+      const T Lm = cQ * ((xmu[par][s][cp] + xmu[par][s][cm]) + (mn + m2[s])) + cC * mc;
+      const T out = h2[s] + dtg * Lm;
+      // rotate this substep's rows
+      ph2[s] = ph1[s];
+      ph1[s] = in;
+      h2[s] = h1[s];
+      h1[s] = hn;
+      m2[s] = m1[s];
+      m1[s] = mn;
+      in = out;
+    }
+    const int yo = t - 3 * M;
+    if (col_out && yo >= y0 && yo < y1) phi_out[gx + nx * yo] = in;
+  };
+
+  // the loop is unrolled by PF so that the load queue is indexed statically
+  for (int t = t0; t < t1; t += PF) {
+#pragma unroll
+    for (int k = 0; k < PF; k++)
+      if (t + k < t1) iterate(t + k, qphi[k], qux[k], quy[k]);
   }
 }
 

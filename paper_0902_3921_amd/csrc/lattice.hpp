@@ -24,6 +24,11 @@ struct D2Q9 {
   __host__ __device__ static constexpr double w(int i) {
     return i == 0 ? 4.0 / 9.0 : (i < 5 ? 1.0 / 9.0 : 1.0 / 36.0);
   }
+  // index of the opposite velocity, e_opp(i) = -e_i
+  __host__ __device__ static constexpr int opp(int i) {
+    constexpr int O[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+    return O[i];
+  }
 };
 
 struct D3Q19 {
@@ -38,6 +43,9 @@ struct D3Q19 {
   }
   __host__ __device__ static constexpr double w(int i) {
     return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+  __host__ __device__ static constexpr int opp(int i) {
+    return i == 0 ? 0 : (i % 2 == 1 ? i + 1 : i - 1);
   }
 };
 

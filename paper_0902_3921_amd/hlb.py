@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ESHAPE", -3: "HLB_EUNSTA
 EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_create",
            "hlb_set_params", "hlb_get_params", "hlb_init_fields", "hlb_set_state", "hlb_get_state",
            "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name",
-           "hlb_last_error", "hlb_destroy", "hlb_version")
+           "hlb_set_plan", "hlb_get_plan", "hlb_autotune", "hlb_last_error", "hlb_destroy", "hlb_version")
 
 
 class HlbError(RuntimeError):
@@ -85,6 +85,9 @@ def load():
         "hlb_reduce": (st, [_vp, ctypes.POINTER(Stats)]),
         "hlb_step_timed": (st, [_vp, ctypes.c_longlong, _dp]),
         "hlb_kernel_name": (ctypes.c_char_p, [_vp, ctypes.c_int]),
+        "hlb_set_plan": (st, [_vp, ctypes.POINTER(ctypes.c_int)]),
+        "hlb_get_plan": (st, [_vp, ctypes.POINTER(ctypes.c_int)]),
+        "hlb_autotune": (st, [_vp, _dp]),
         "hlb_last_error": (ctypes.c_char_p, [_vp]),
         "hlb_destroy": (st, [_vp]),
         "hlb_version": (ctypes.c_char_p, []),
@@ -244,6 +247,21 @@ class Sim:
         ms = (ctypes.c_double * 2)()
         _check(self.lib.hlb_step_timed(self.ctx, int(nsteps), ms), self.ctx)
         return float(ms[0]), float(ms[1])
+
+    @property
+    def plan(self):
+        pl = (ctypes.c_int * 4)()
+        _check(self.lib.hlb_get_plan(self.ctx, pl), self.ctx)
+        return tuple(pl)
+
+    def set_plan(self, kind, fuse=1, bw=128, seg=64):
+        pl = (ctypes.c_int * 4)(kind, fuse, bw, seg)
+        _check(self.lib.hlb_set_plan(self.ctx, pl), self.ctx)
+
+    def autotune(self) -> float:
+        us = ctypes.c_double()
+        _check(self.lib.hlb_autotune(self.ctx, ctypes.byref(us)), self.ctx)
+        return us.value
 
     def kernel_name(self, cls: int) -> str:
         return self.lib.hlb_kernel_name(self.ctx, cls).decode()

@@ -242,3 +242,72 @@ def test_nonfinite_state_is_reported(hlb):
     gpu.init(np.zeros(shape))
     gpu.step(1)
     assert gpu.reduce()["finite"]
+
+
+@pytest.mark.parametrize("plan", [(0, 1, 128, 64), (1, 5, 64, 7), (1, 5, 128, 16), (1, 5, 256, 40),
+                                  (1, 2, 64, 9), (1, 3, 128, 100), (1, 1, 64, 1)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_substep_plans_agree(hlb, plan, storage):
+    """Every execution plan of the convection-diffusion substeps (one launch
+    per substep, or fused y-marching launches of several substeps with
+    various block shapes) computes the same step: ragged 150 x 83 lattice,
+    m = 5 split into fused launches of plan[1] substeps."""
+    if storage == "f64" and plan[2] == 256:
+        pytest.skip("bw = 256 needs float storage")
+    shape = (83, 150)
+    phi = _drop(shape, 20, BASE) + synth.spinodal(shape, seed=5, amp=0.02)
+    u0 = np.zeros((2,) + shape)
+    u0[0], u0[1] = 0.01, -0.007
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=0.3, Q=2.5, advection=plan[3] % 2)
+    gpu.set_plan(*plan)
+    assert gpu.plan == plan
+    gpu.step(40)
+    ora.step(40)
+    d = _maxdiff(gpu, ora)
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert max(d.values()) < tol, (plan, d)
+
+
+def test_fused_plan_on_lattices_smaller_than_the_halo(hlb):
+    """The fused kernel's strip and march wrap around lattices narrower or
+    shorter than its halo (3 rows per fused substep)."""
+    for shape in [(7, 9), (40, 5), (3, 100)]:
+        phi = synth.spinodal(shape, seed=sum(shape), amp=0.3)
+        gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=0.3, Q=2.5)
+        gpu.set_plan(1, 5, 64, 4)
+        gpu.step(6)
+        ora.step(6)
+        d = _maxdiff(gpu, ora)
+        assert max(d.values()) < 1e-13, (shape, d)
+
+
+def test_invalid_plans_rejected(hlb):
+    gpu = hlb.Sim((32, 32), "f64", **BASE)
+    for bad in [(2, 1, 64, 8), (1, 6, 128, 8), (1, 5, 96, 8), (1, 5, 256, 8), (1, 1, 64, 0), (1, 5, 32, 8)]:
+        with pytest.raises(hlb.HlbError) as e:
+            gpu.set_plan(*bad)
+        assert e.value.status == hlb.HLB_EINVAL
+    g3 = hlb.Sim((8, 8, 8), "f32", **BASE)
+    with pytest.raises(hlb.HlbError):
+        g3.set_plan(1, 5, 128, 8)
+    g2 = hlb.Sim((32, 32), "f32", **BASE, cd_Q=2 / 3)
+    assert g2.plan[0] == 0
+    with pytest.raises(hlb.HlbError):
+        g2.set_plan(1, 3, 128, 8)
+
+
+def test_autotune_keeps_state_and_parity(hlb):
+    shape = (256, 256)
+    phi = synth.spinodal(shape, seed=2)
+    gpu, ora = _pair(hlb, shape, "f32", phi, **BASE, N=0.3, Q=2.5)
+    gpu.step(5)
+    ora.step(5)
+    before = gpu.state()
+    us = gpu.autotune()
+    after = gpu.state()
+    assert us > 0
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    gpu.step(20)
+    ora.step(20)
+    d = _maxdiff(gpu, ora)
+    assert d["phi"] < 1e-5 and d["u"] < 1e-5, (gpu.plan, d)
