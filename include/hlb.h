@@ -175,13 +175,16 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
 
 /* Execution plan of the convection-diffusion substeps (a performance
  * choice; every plan computes the same values up to rounding order):
- *   plan[0] kind: 0 = one tiled launch per substep (any lattice);
- *                 1 = fused launches that march along y and run plan[1]
- *                     substeps per pass (D2Q9 with cd_Q = 1 only);
- *   plan[1] fuse: substeps per fused launch, 1..5;
- *   plan[2] bw:   columns per block of the fused kernel, 64, 128 or 256
- *                 (256 with HLB_F32_SHIFTED only), bw - 6*fuse >= 16;
- *   plan[3] seg:  rows per block of the fused kernel, >= 1.
+ *   plan[0] kind: 0 = one tiled launch per substep (any lattice, any cd_Q);
+ *                 1 = marching launches (cd_Q = 1 only): in D2Q9 a launch
+ *                     marches along y and runs plan[1] substeps; in D3Q19 a
+ *                     launch marches along z and runs one substep;
+ *   plan[1] fuse: substeps per launch, 1..5 (D2Q9), 1 (D3Q19);
+ *   plan[2] bw:   D2Q9: columns per block, 64, 128 or 256 (256 with
+ *                 HLB_F32_SHIFTED only), bw - 6*fuse >= 16;
+ *                 D3Q19: threads per block, 256 (16x16), 512 (32x16) or
+ *                 1024 (64x16) (512 and 1024 with HLB_F32_SHIFTED only);
+ *   plan[3] seg:  rows (D2Q9) or planes (D3Q19) per block, >= 1.
  * hlb_create picks a plan from the lattice size; hlb_set_plan overrides it
  * (HLB_EINVAL if the plan cannot run this context).  hlb_set_params keeps a
  * user plan while it stays valid. */

@@ -339,7 +339,27 @@ struct Ops {
     }
   }
   // one fused launch of M substeps: phi[phicur] -> phi[1 - phicur]
+  template <int TXI, int TYI>
+  static void march3_1(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
+    const dim3 grid(ceil_div(c->nx, TXI - 6), ceil_div(c->ny, TYI - 6), ceil_div(c->nz, c->plan.seg));
+    if (k.advection == 1)
+      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYI, true>), grid, dim3(TXI * TYI), 0, c->stream, k, c->plan.seg,
+                         src, at<T>(c, c->lay.u), dst);
+    else
+      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYI, false>), grid, dim3(TXI * TYI), 0, c->stream, k, c->plan.seg,
+                         src, at<T>(c, c->lay.u), dst);
+  }
   static void march(hlb_ctx *c, const KParams &k, int M) {
+    if constexpr (L::D == 3) {
+      (void)M;
+      const T *src = at<T>(c, c->lay.phi[c->phicur]);
+      T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
+      if (c->plan.bw == 256) march3_1<16, 16>(c, k, src, dst);
+      else if constexpr (sizeof(T) == 4) {
+        if (c->plan.bw == 512) march3_1<32, 16>(c, k, src, dst);
+        else march3_1<64, 16>(c, k, src, dst);
+      }
+    }
     if constexpr (L::D == 2) {
       const T *src = at<T>(c, c->lay.phi[c->phicur]);
       T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
@@ -448,9 +468,29 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
     *why = "plan kind must be 0 or 1";
     return false;
   }
-  if (c->lattice != HLB_D2Q9 || c->p.cd_Q != 1.0) {
-    *why = "the fused substep kernel needs D2Q9 and cd_Q = 1";
+  if (c->p.cd_Q != 1.0) {
+    *why = "the marching substep kernels need cd_Q = 1";
     return false;
+  }
+  if (c->lattice == HLB_D3Q19) {
+    // 3D: one substep per launch; bw = threads per block (256: 16x16, 512: 32x16, 1024: 64x16)
+    if (pl.fuse != 1) {
+      *why = "the 3D marching kernel runs one substep per launch (fuse = 1)";
+      return false;
+    }
+    if (pl.bw != 256 && pl.bw != 512 && pl.bw != 1024) {
+      *why = "3D bw must be 256, 512 or 1024";
+      return false;
+    }
+    if (c->storage == HLB_F64 && pl.bw != 256) {
+      *why = "3D double storage needs bw = 256 (LDS size)";
+      return false;
+    }
+    if (pl.seg < 1) {
+      *why = "seg must be >= 1";
+      return false;
+    }
+    return true;
   }
   if (pl.fuse < 1 || pl.fuse > 5) {
     *why = "fuse must be in 1..5";
@@ -477,7 +517,17 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
 
 ChPlan default_plan(const hlb_ctx *c) {
   ChPlan pl{0, 1, 128, 64};
-  if (c->lattice != HLB_D2Q9 || c->p.cd_Q != 1.0) return pl;
+  if (c->p.cd_Q != 1.0) return pl;
+  if (c->lattice == HLB_D3Q19) {
+    pl.kind = 1;
+    pl.fuse = 1;
+    pl.bw = c->storage == HLB_F64 ? 256 : 512;
+    const int ox = pl.bw == 256 ? 10 : 26, oy = 10;
+    const long long cols = (long long)ceil_div(c->nx, ox) * ceil_div(c->ny, oy);
+    long long seg = (long long)c->nz * cols / 1024;
+    pl.seg = (int)std::max(8LL, std::min<long long>(seg, c->nz));
+    return pl;
+  }
   pl.kind = 1;
   pl.fuse = std::min(c->m, 5);
   pl.bw = pl.fuse <= 2 ? 64 : 128;
@@ -796,8 +846,12 @@ const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
   if (cls == 1 && c->plan.kind == 1) {
     hlb_ctx *mc = const_cast<hlb_ctx *>(c);
     char buf[160];
-    snprintf(buf, sizeof buf, "hlb::k_ch_march<%s, %d, %d>", c->storage == HLB_F64 ? "double" : "float",
-             std::min(c->plan.fuse, c->m), c->plan.bw);
+    if (c->lattice == HLB_D3Q19)
+      snprintf(buf, sizeof buf, "hlb::k_ch_march3<%s, %d threads>", c->storage == HLB_F64 ? "double" : "float",
+               c->plan.bw);
+    else
+      snprintf(buf, sizeof buf, "hlb::k_ch_march<%s, %d, %d>", c->storage == HLB_F64 ? "double" : "float",
+               std::min(c->plan.fuse, c->m), c->plan.bw);
     mc->names[1] = buf;
   } else if (cls == 1) {
     const_cast<hlb_ctx *>(c)->names[1] = kernel_names(c->lattice, c->storage, 1);
@@ -831,14 +885,22 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   // the current phi and writes the spare buffer, so the state is unchanged
   std::vector<ChPlan> cand;
   cand.push_back(ChPlan{0, 1, 128, 64});
-  if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
-    const int fuse = std::min(c->m, 5);
-    for (int bw : {64, 128, 256})
-      for (int seg : {8, 16, 32, 64, 128, 256}) {
-        ChPlan pl{1, fuse, bw, seg};
+  if (c->lattice == HLB_D3Q19 && c->p.cd_Q == 1.0) {
+    for (int bw : {256, 512, 1024})
+      for (int seg : {8, 16, 32, 64, 128}) {
+        ChPlan pl{1, 1, bw, seg};
         std::string why;
         if (plan_valid(c, pl, &why)) cand.push_back(pl);
       }
+  }
+  if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
+    for (int fuse = 1; fuse <= std::min(c->m, 5); fuse++)
+      for (int bw : {64, 128, 256})
+        for (int seg : {8, 16, 32, 64, 128, 256}) {
+          ChPlan pl{1, fuse, bw, seg};
+          std::string why;
+          if (plan_valid(c, pl, &why)) cand.push_back(pl);
+        }
   }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)

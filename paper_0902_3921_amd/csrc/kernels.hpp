@@ -478,23 +478,23 @@ __global__ void __launch_bounds__(NT) k_ch(KParams p, const T *__restrict__ phi_
 
 // M convection-diffusion substeps in one pass (2D, standard 5-point
 // Laplacian).  A block of BW threads owns BW consecutive lattice columns
-// (one per thread) and marches along y.  Substep s runs 3 rows behind
-// substep s-1, because one substep of Sec. 2.3 reads phi three rows away
-// (advection 1 + the two Laplacians of Eq. diff); its output row is the next
-// input row of substep s+1, in a register of the same thread.  Each thread
-// keeps, per substep, the last three rows of phi^s, h and the diffusion
-// potential of its column in registers (the y neighbours); the x neighbours
-// come from one LDS row per quantity that every thread publishes at the
-// start of an iteration, and u* from an LDS ring of its last 3M+1 rows.  One
-// barrier per row.  Output columns: the middle BW - 6M; output rows: the
-// segment [y0, y1) of the block; the march starts 3M rows before y0 and
-// ends 3M rows after y1 - 1.  phi and u* are read once and phi' written once
-// per site for all M substeps.
+// (one per thread) and marches along y.  One substep of Sec. 2.3 reads phi
+// three rows away (advection 1 + the two Laplacians of Eq. diff), so the
+// output row of substep s trails its newest input row by 3; substep s+1
+// takes that row as input one iteration later, so every substep of an
+// iteration works on values of the previous iteration and the M substeps
+// are independent instruction streams (substep s runs 4s rows behind the
+// input).  Each thread keeps, per substep, the last rows of phi^s, h and the
+// diffusion potential of its column in registers (the y neighbours); the x
+// neighbours come from one LDS row per quantity that every thread publishes
+// at the start of an iteration, and u* from an LDS ring of its last 4M rows.
+// One barrier per row.  Output columns: the middle BW - 6M; output rows: the
+// segment [y0, y1) of the block.  phi and u* are read once and phi' written
+// once per site for all M substeps.
 template <typename T, int M, int BW, bool FLUX>
 __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__restrict__ phi_in,
                                                  const T *__restrict__ u, T *__restrict__ phi_out) {
-  constexpr int R = 3 * M + 1;  // rows of the u* ring
-  constexpr int PF = 1;         // rows loaded ahead of use
+  constexpr int R = 4 * M;  // rows of the u* ring
   __shared__ T xphi[2][M][BW], xh[2][M][BW], xmu[2][M][BW];
   __shared__ T sux[R][BW], suy[R][BW];
   const int nx = p.nx, ny = p.ny;
@@ -508,56 +508,49 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
   const T *ux_g = u, *uy_g = u + ns;
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
-  const bool wide = ny >= 3 * M + PF;  // rows wrap at most once
+  const int t0 = y0 - 3 * M, t1 = y1 + 4 * M - 1;  // iterations [t0, t1)
+  const bool wide = ny >= 4 * M;                    // rows in [t0, t1] wrap at most once
 
-  // per substep: phi rows (t-3s-2, t-3s-1), h rows (t-3s-3, t-3s-2), mu rows (t-3s-4, t-3s-3)
-  T ph2[M], ph1[M], h2[M], h1[M], m2[M], m1[M];
+  // substep s at iteration t: newest input row t-4s; registers hold
+  // phi rows (t-4s-2, t-4s-1), h rows (t-4s-3, t-4s-2), mu rows (t-4s-4, t-4s-3),
+  // and carry[s] = the row phi^s(t-4s) produced by substep s-1 last iteration
+  T ph2[M], ph1[M], h2[M], h1[M], m2[M], m1[M], carry[M];
 #pragma unroll
-  for (int s = 0; s < M; s++) ph2[s] = ph1[s] = h2[s] = h1[s] = m2[s] = m1[s] = T(0);
+  for (int s = 0; s < M; s++) ph2[s] = ph1[s] = h2[s] = h1[s] = m2[s] = m1[s] = carry[s] = T(0);
 
-  const int t0 = y0 - 3 * M, t1 = y1 + 3 * M;  // iterations [t0, t1)
   auto row_of = [&](int t) { return wide ? wrap1(t, ny) : wrapc(t, ny); };
-  // input rows t .. t + PF - 1 in flight, slot (t - t0) % PF
-  T qphi[PF], qux[PF], quy[PF];
-#pragma unroll
-  for (int k = 0; k < PF; k++) {
-    qphi[k] = qux[k] = quy[k] = T(0);
-    if (t0 + k < t1) {
-      const int g = gx + nx * row_of(t0 + k);
-      qphi[k] = phi_in[g];
-      qux[k] = ux_g[g];
-      quy[k] = uy_g[g];
-    }
-  }
-
-  auto iterate = [&](int t, T &rphi, T &rux, T &ruy) {
+  int g = gx + nx * row_of(t0);
+  T nphi = phi_in[g], nux = ux_g[g], nuy = uy_g[g];
+  for (int t = t0; t < t1; t++) {
     const int par = t & 1;
     const int slot = (t - t0) % R;
     // publish last iteration's rows and the new u* row
-    sux[slot][c] = rux;
-    suy[slot][c] = ruy;
+    sux[slot][c] = nux;
+    suy[slot][c] = nuy;
 #pragma unroll
     for (int s = 0; s < M; s++) {
       xphi[par][s][c] = ph1[s];
       xh[par][s][c] = h1[s];
       xmu[par][s][c] = m1[s];
     }
-    T in = rphi;  // phi^0 row t
-    if (t + PF < t1) {  // refill this queue slot with row t + PF
-      const int g = gx + nx * row_of(t + PF);
-      rphi = phi_in[g];
-      rux = ux_g[g];
-      ruy = uy_g[g];
+    carry[0] = nphi;  // phi^0 row t
+    if (t + 1 < t1) {  // prefetch row t + 1
+      g = gx + nx * row_of(t + 1);
+      nphi = phi_in[g];
+      nux = ux_g[g];
+      nuy = uy_g[g];
     }
     __syncthreads();
+    T last = T(0);
+    // substeps in reverse order: substep s reads carry[s] before substep s-1 replaces it
 #pragma unroll
-    for (int s = 0; s < M; s++) {
-      // u* rows t-3s-2 (below), t-3s-1 (centre), t-3s (above) of the ring
-      int kc = (t - t0 - 3 * s - 1) % R;
+    for (int s = M - 1; s >= 0; s--) {
+      // u* rows t-4s-2 (below), t-4s-1 (centre), t-4s (above) of the ring
+      int kc = (t - t0 - 4 * s - 1) % R;
       kc += kc < 0 ? R : 0;
       const int kd = kc == 0 ? R - 1 : kc - 1, ku = kc == R - 1 ? 0 : kc + 1;
-      // advection half-step at row t-3s-1
-      const T pc = ph1[s], pdn = ph2[s], pup = in;
+      // advection half-step at row t-4s-1
+      const T pc = ph1[s], pdn = ph2[s], pup = carry[s];
       const T pw = xphi[par][s][cm], pe = xphi[par][s][cp];
       const T uxc = sux[kc][c], uxw = sux[kc][cm], uxe = sux[kc][cp];
       const T uyc = suy[kc][c], uyd = suy[kd][c], uyu = suy[ku][c];
@@ -574,33 +567,129 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
         rhs = tx + ty;
       }
       const T hn = pc - dt * rhs;
-      // diffusion potential at row t-3s-2: a h + b phi^3 - kappa L h
+      // diffusion potential at row t-4s-2: a h + b phi^3 - kappa L h
       const T hc = h1[s];
       const T Lh = cQ * ((xh[par][s][cp] + xh[par][s][cm]) + (hn + h2[s])) + cC * hc;
       const T ps = ph2[s];
       const T mn = a * hc + b * ps * ps * ps - kappa * Lh;
-      // phi^{s+1} at row t-3s-3: h + dt Gamma L mu
+      // phi^{s+1} at row t-4s-3: h + dt Gamma L mu
       const T mc = m1[s];
       const T Lm = cQ * ((xmu[par][s][cp] + xmu[par][s][cm]) + (mn + m2[s])) + cC * mc;
       const T out = h2[s] + dtg * Lm;
       // rotate this substep's rows
       ph2[s] = ph1[s];
-      ph1[s] = in;
+      ph1[s] = carry[s];
       h2[s] = h1[s];
       h1[s] = hn;
       m2[s] = m1[s];
       m1[s] = mn;
-      in = out;
+      if (s + 1 < M) carry[s + 1] = out;
+      else last = out;
     }
-    const int yo = t - 3 * M;
-    if (col_out && yo >= y0 && yo < y1) phi_out[gx + nx * yo] = in;
-  };
+    const int yo = t - 4 * M + 1;  // row of the last substep's output
+    if (col_out && yo >= y0 && yo < y1) phi_out[gx + nx * yo] = last;
+  }
+}
 
-  // the loop is unrolled by PF so that the load queue is indexed statically
-  for (int t = t0; t < t1; t += PF) {
-#pragma unroll
-    for (int k = 0; k < PF; k++)
-      if (t + k < t1) iterate(t + k, qphi[k], qux[k], quy[k]);
+// One convection-diffusion substep in 3D (standard 7-point Laplacian),
+// marching along z.  A block of TXI x TYI threads owns that many (x, y)
+// columns (one per thread) and walks the z planes of its segment; the
+// output is the middle (TXI - 6) x (TYI - 6) columns.  Per column the last
+// planes of phi, h and the diffusion potential live in registers (the z
+// neighbours); the x and y neighbours come from one LDS plane per quantity
+// published at the start of an iteration, and u* from an LDS ring of four
+// planes.  The output plane trails the input plane by 3.  One barrier per
+// plane; phi and u* are read once and phi' written once per site.
+template <typename T, int TXI, int TYI, bool FLUX>
+__global__ void __launch_bounds__(TXI *TYI) k_ch_march3(KParams p, int seg, const T *__restrict__ phi_in,
+                                                        const T *__restrict__ u, T *__restrict__ phi_out) {
+  constexpr int R = 4;  // planes of the u* ring
+  __shared__ T xphi[2][TYI][TXI], xh[2][TYI][TXI], xmu[2][TYI][TXI];
+  __shared__ T sux[R][TYI][TXI], suy[R][TYI][TXI], suz[R][TYI][TXI];
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int cx = threadIdx.x % TXI, cy = threadIdx.x / TXI;
+  const int X0 = blockIdx.x * (TXI - 6), Y0 = blockIdx.y * (TYI - 6);
+  const int z0 = blockIdx.z * seg, z1 = min(z0 + seg, nz);
+  const int gx = wrapc(X0 - 3 + cx, nx), gy = wrapc(Y0 - 3 + cy, ny);
+  const bool col_out = cx >= 3 && cx < TXI - 3 && cy >= 3 && cy < TYI - 3 && X0 + cx - 3 < nx && Y0 + cy - 3 < ny;
+  // edge lanes read themselves; their results are never used
+  const int cxm = cx > 0 ? cx - 1 : 0, cxp = cx < TXI - 1 ? cx + 1 : TXI - 1;
+  const int cym = cy > 0 ? cy - 1 : 0, cyp = cy < TYI - 1 ? cy + 1 : TYI - 1;
+  const size_t ns = (size_t)p.ns;
+  const T *ux_g = u, *uy_g = u + ns, *uz_g = u + 2 * ns;
+  const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
+  const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
+  const int t0 = z0 - 3, t1 = z1 + 3;  // iterations [t0, t1); output plane t - 3
+  const bool wide = nz >= 4;
+  const int col = gx + nx * gy;
+  const size_t plane = (size_t)nx * ny;
+  auto plane_of = [&](int t) { return wide ? wrap1(t, nz) : wrapc(t, nz); };
+
+  // registers: phi planes (t-2, t-1), h planes (t-3, t-2), mu planes (t-4, t-3)
+  T ph2 = T(0), ph1 = T(0), h2 = T(0), h1 = T(0), m2 = T(0), m1 = T(0);
+  size_t g = col + plane * plane_of(t0);
+  T nphi = phi_in[g], nux = ux_g[g], nuy = uy_g[g], nuz = uz_g[g];
+  for (int t = t0; t < t1; t++) {
+    const int par = t & 1;
+    const int slot = (t - t0) & (R - 1);
+    sux[slot][cy][cx] = nux;
+    suy[slot][cy][cx] = nuy;
+    suz[slot][cy][cx] = nuz;
+    xphi[par][cy][cx] = ph1;
+    xh[par][cy][cx] = h1;
+    xmu[par][cy][cx] = m1;
+    const T in = nphi;  // phi plane t
+    if (t + 1 < t1) {
+      g = col + plane * plane_of(t + 1);
+      nphi = phi_in[g];
+      nux = ux_g[g];
+      nuy = uy_g[g];
+      nuz = uz_g[g];
+    }
+    __syncthreads();
+    const int kc = (t - t0 - 1) & (R - 1), kd = (t - t0 - 2) & (R - 1), ku = (t - t0) & (R - 1);
+    // advection half-step at plane t-1
+    const T pc = ph1;
+    const T pw = xphi[par][cy][cxm], pe = xphi[par][cy][cxp];
+    const T ps_ = xphi[par][cym][cx], pn = xphi[par][cyp][cx];
+    const T pd = ph2, pu = in;
+    const T uxc = sux[kc][cy][cx], uxw = sux[kc][cy][cxm], uxe = sux[kc][cy][cxp];
+    const T uyc = suy[kc][cy][cx], uys = suy[kc][cym][cx], uyn = suy[kc][cyp][cx];
+    const T uzc = suz[kc][cy][cx], uzd = suz[kd][cy][cx], uzu = suz[ku][cy][cx];
+    T rhs;
+    if constexpr (!FLUX) {
+      const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
+      const T ty = pc * ((uyn - uys) * T(0.5)) + uyc * (uyc > T(0) ? pc - ps_ : pn - pc);
+      const T tz = pc * ((uzu - uzd) * T(0.5)) + uzc * (uzc > T(0) ? pc - pd : pu - pc);
+      rhs = tx + ty + tz;
+    } else {
+      const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
+      const T vyn = (uyc + uyn) * T(0.5), vys = (uys + uyc) * T(0.5);
+      const T vzu = (uzc + uzu) * T(0.5), vzd = (uzd + uzc) * T(0.5);
+      const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
+      const T ty = (vyn > T(0) ? vyn * pc : vyn * pn) - (vys > T(0) ? vys * ps_ : vys * pc);
+      const T tz = (vzu > T(0) ? vzu * pc : vzu * pu) - (vzd > T(0) ? vzd * pd : vzd * pc);
+      rhs = tx + ty + tz;
+    }
+    const T hn = pc - dt * rhs;
+    // diffusion potential at plane t-2
+    const T hc = h1;
+    const T Lh = cQ * ((xh[par][cy][cxp] + xh[par][cy][cxm]) + (xh[par][cyp][cx] + xh[par][cym][cx]) +
+                       (hn + h2)) + cC * hc;
+    const T mn = a * hc + b * ph2 * ph2 * ph2 - kappa * Lh;
+    // phi' at plane t-3
+    const T mc = m1;
+    const T Lm = cQ * ((xmu[par][cy][cxp] + xmu[par][cy][cxm]) + (xmu[par][cyp][cx] + xmu[par][cym][cx]) +
+                       (mn + m2)) + cC * mc;
+    const T out = h2 + dtg * Lm;
+    ph2 = ph1;
+    ph1 = in;
+    h2 = h1;
+    h1 = hn;
+    m2 = m1;
+    m1 = mn;
+    const int zo = t - 3;
+    if (col_out && zo >= z0 && zo < z1) phi_out[col + plane * zo] = out;
   }
 }
 

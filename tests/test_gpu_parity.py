@@ -288,8 +288,12 @@ def test_invalid_plans_rejected(hlb):
             gpu.set_plan(*bad)
         assert e.value.status == hlb.HLB_EINVAL
     g3 = hlb.Sim((8, 8, 8), "f32", **BASE)
+    for bad in [(1, 5, 128, 8), (1, 1, 128, 8), (1, 2, 512, 8)]:
+        with pytest.raises(hlb.HlbError):
+            g3.set_plan(*bad)
+    g3d = hlb.Sim((8, 8, 8), "f64", **BASE)
     with pytest.raises(hlb.HlbError):
-        g3.set_plan(1, 5, 128, 8)
+        g3d.set_plan(1, 1, 512, 8)
     g2 = hlb.Sim((32, 32), "f32", **BASE, cd_Q=2 / 3)
     assert g2.plan[0] == 0
     with pytest.raises(hlb.HlbError):
@@ -311,3 +315,38 @@ def test_autotune_keeps_state_and_parity(hlb):
     ora.step(20)
     d = _maxdiff(gpu, ora)
     assert d["phi"] < 1e-5 and d["u"] < 1e-5, (gpu.plan, d)
+
+
+@pytest.mark.parametrize("plan", [(0, 1, 128, 64), (1, 1, 256, 5), (1, 1, 512, 7), (1, 1, 1024, 16)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("advection", [0, 1])
+def test_d3q19_substep_plans_agree(hlb, plan, storage, advection):
+    """The 3D z-marching substep kernel (block shapes 16x16, 32x16, 64x16,
+    various segment heights) and the tiled kernel give the oracle's step on
+    a ragged 70 x 37 x 21 lattice."""
+    if storage == "f64" and plan[2] > 256:
+        pytest.skip("bw > 256 needs float storage")
+    shape = (21, 37, 70)
+    phi = _drop(shape, 8, BASE) + synth.spinodal(shape, seed=9, amp=0.02)
+    u0 = np.zeros((3,) + shape)
+    u0[0], u0[1], u0[2] = 0.004, -0.006, 0.005
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=1 / 6, Q=1 / 3, advection=advection)
+    gpu.set_plan(*plan)
+    gpu.step(4)
+    ora.step(4)
+    d = _maxdiff(gpu, ora)
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert max(d.values()) < tol, (plan, d)
+
+
+def test_d3q19_march_thin_lattices(hlb):
+    """z-marching with fewer planes than its halo, and x-y tiles wider than
+    the lattice (periodic images)."""
+    for shape in [(3, 12, 40), (9, 5, 6), (1, 8, 8)]:
+        phi = synth.spinodal(shape, seed=sum(shape), amp=0.3)
+        gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=1 / 6, Q=1 / 3)
+        gpu.set_plan(1, 1, 256, 2)
+        gpu.step(3)
+        ora.step(3)
+        d = _maxdiff(gpu, ora)
+        assert max(d.values()) < 1e-13, (shape, d)
