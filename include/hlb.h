@@ -182,8 +182,9 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
  *   plan[1] fuse: substeps per launch, 1..5 (D2Q9), 1 (D3Q19);
  *   plan[2] bw:   D2Q9: columns per block, 64, 128 or 256 (256 with
  *                 HLB_F32_SHIFTED only), bw - 6*fuse >= 16;
- *                 D3Q19: threads per block, 256 (16x16), 512 (32x16) or
- *                 1024 (64x16) (512 and 1024 with HLB_F32_SHIFTED only);
+ *                 D3Q19: threads per block, each owning two (x, y)
+ *                 columns: 256 (16x32 columns), 512 (32x32) or 1024 (64x32,
+ *                 HLB_F32_SHIFTED only);
  *   plan[3] seg:  rows (D2Q9) or planes (D3Q19) per block, >= 1.
  * hlb_create picks a plan from the lattice size; hlb_set_plan overrides it
  * (HLB_EINVAL if the plan cannot run this context).  hlb_set_params keeps a

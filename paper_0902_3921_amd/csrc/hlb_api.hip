@@ -339,14 +339,15 @@ struct Ops {
     }
   }
   // one fused launch of M substeps: phi[phicur] -> phi[1 - phicur]
-  template <int TXI, int TYI>
+  // TXI x TYT threads, two y rows each: output (TXI - 6) x (2 TYT - 6) columns per block
+  template <int TXI, int TYT>
   static void march3_1(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
-    const dim3 grid(ceil_div(c->nx, TXI - 6), ceil_div(c->ny, TYI - 6), ceil_div(c->nz, c->plan.seg));
+    const dim3 grid(ceil_div(c->nx, TXI - 6), ceil_div(c->ny, 2 * TYT - 6), ceil_div(c->nz, c->plan.seg));
     if (k.advection == 1)
-      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYI, true>), grid, dim3(TXI * TYI), 0, c->stream, k, c->plan.seg,
+      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYT, true>), grid, dim3(TXI * TYT), 0, c->stream, k, c->plan.seg,
                          src, at<T>(c, c->lay.u), dst);
     else
-      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYI, false>), grid, dim3(TXI * TYI), 0, c->stream, k, c->plan.seg,
+      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYT, false>), grid, dim3(TXI * TYT), 0, c->stream, k, c->plan.seg,
                          src, at<T>(c, c->lay.u), dst);
   }
   static void march(hlb_ctx *c, const KParams &k, int M) {
@@ -355,10 +356,8 @@ struct Ops {
       const T *src = at<T>(c, c->lay.phi[c->phicur]);
       T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
       if (c->plan.bw == 256) march3_1<16, 16>(c, k, src, dst);
-      else if constexpr (sizeof(T) == 4) {
-        if (c->plan.bw == 512) march3_1<32, 16>(c, k, src, dst);
-        else march3_1<64, 16>(c, k, src, dst);
-      }
+      else if (c->plan.bw == 512) march3_1<32, 16>(c, k, src, dst);
+      else if constexpr (sizeof(T) == 4) march3_1<64, 16>(c, k, src, dst);
     }
     if constexpr (L::D == 2) {
       const T *src = at<T>(c, c->lay.phi[c->phicur]);
@@ -482,8 +481,8 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
       *why = "3D bw must be 256, 512 or 1024";
       return false;
     }
-    if (c->storage == HLB_F64 && pl.bw != 256) {
-      *why = "3D double storage needs bw = 256 (LDS size)";
+    if (c->storage == HLB_F64 && pl.bw == 1024) {
+      *why = "3D double storage needs bw <= 512 (LDS size)";
       return false;
     }
     if (pl.seg < 1) {
@@ -521,8 +520,8 @@ ChPlan default_plan(const hlb_ctx *c) {
   if (c->lattice == HLB_D3Q19) {
     pl.kind = 1;
     pl.fuse = 1;
-    pl.bw = c->storage == HLB_F64 ? 256 : 512;
-    const int ox = pl.bw == 256 ? 10 : 26, oy = 10;
+    pl.bw = 512;  // 32 x 32 columns, 26 x 26 outputs per block
+    const int ox = 26, oy = 26;
     const long long cols = (long long)ceil_div(c->nx, ox) * ceil_div(c->ny, oy);
     long long seg = (long long)c->nz * cols / 1024;
     pl.seg = (int)std::max(8LL, std::min<long long>(seg, c->nz));

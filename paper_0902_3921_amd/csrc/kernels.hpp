@@ -509,7 +509,7 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
   const int t0 = y0 - 3 * M, t1 = y1 + 4 * M - 1;  // iterations [t0, t1)
-  const bool wide = ny >= 4 * M;                    // rows in [t0, t1] wrap at most once
+  const bool wide = ny >= 4 * M + 1;                // rows in [t0, t1] wrap at most once
 
   // substep s at iteration t: newest input row t-4s; registers hold
   // phi rows (t-4s-2, t-4s-1), h rows (t-4s-3, t-4s-2), mu rows (t-4s-4, t-4s-3),
@@ -519,26 +519,37 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
   for (int s = 0; s < M; s++) ph2[s] = ph1[s] = h2[s] = h1[s] = m2[s] = m1[s] = carry[s] = T(0);
 
   auto row_of = [&](int t) { return wide ? wrap1(t, ny) : wrapc(t, ny); };
-  int g = gx + nx * row_of(t0);
-  T nphi = phi_in[g], nux = ux_g[g], nuy = uy_g[g];
-  for (int t = t0; t < t1; t++) {
-    const int par = t & 1;
+  // input rows in flight: queue slot k holds row t0 + k + 2j at its j-th use
+  T qphi[2], qux[2], quy[2];
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    qphi[k] = qux[k] = quy[k] = T(0);
+    if (t0 + k < t1) {
+      const int g = gx + nx * row_of(t0 + k);
+      qphi[k] = phi_in[g];
+      qux[k] = ux_g[g];
+      quy[k] = uy_g[g];
+    }
+  }
+  // one iteration: input row t from queue slot k (parity of the published rows = k)
+  auto iterate = [&](const int t, const int k) {
+    const int par = k;
     const int slot = (t - t0) % R;
     // publish last iteration's rows and the new u* row
-    sux[slot][c] = nux;
-    suy[slot][c] = nuy;
+    sux[slot][c] = qux[k];
+    suy[slot][c] = quy[k];
 #pragma unroll
     for (int s = 0; s < M; s++) {
       xphi[par][s][c] = ph1[s];
       xh[par][s][c] = h1[s];
       xmu[par][s][c] = m1[s];
     }
-    carry[0] = nphi;  // phi^0 row t
-    if (t + 1 < t1) {  // prefetch row t + 1
-      g = gx + nx * row_of(t + 1);
-      nphi = phi_in[g];
-      nux = ux_g[g];
-      nuy = uy_g[g];
+    carry[0] = qphi[k];  // phi^0 row t
+    if (t + 2 < t1) {    // refill the slot with row t + 2
+      const int g = gx + nx * row_of(t + 2);
+      qphi[k] = phi_in[g];
+      qux[k] = ux_g[g];
+      quy[k] = uy_g[g];
     }
     __syncthreads();
     T last = T(0);
@@ -588,108 +599,174 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
     }
     const int yo = t - 4 * M + 1;  // row of the last substep's output
     if (col_out && yo >= y0 && yo < y1) phi_out[gx + nx * yo] = last;
+  };
+  // unrolled by two so the queue slot and the parity are static
+  for (int t = t0; t < t1; t += 2) {
+    iterate(t, 0);
+    if (t + 1 < t1) iterate(t + 1, 1);
   }
 }
 
 // One convection-diffusion substep in 3D (standard 7-point Laplacian),
-// marching along z.  A block of TXI x TYI threads owns that many (x, y)
-// columns (one per thread) and walks the z planes of its segment; the
-// output is the middle (TXI - 6) x (TYI - 6) columns.  Per column the last
-// planes of phi, h and the diffusion potential live in registers (the z
-// neighbours); the x and y neighbours come from one LDS plane per quantity
-// published at the start of an iteration, and u* from an LDS ring of four
-// planes.  The output plane trails the input plane by 3.  One barrier per
-// plane; phi and u* are read once and phi' written once per site.
-template <typename T, int TXI, int TYI, bool FLUX>
-__global__ void __launch_bounds__(TXI *TYI) k_ch_march3(KParams p, int seg, const T *__restrict__ phi_in,
+// marching along z.  A block of TXI x TYT threads owns TXI x 2 TYT (x, y)
+// columns, two neighbouring rows per thread, and walks the z planes of its
+// segment; the output is the middle (TXI - 6) x (2 TYT - 6) columns.  Per
+// column the last planes of phi, h, the diffusion potential and u*_z live in
+// registers (the z neighbours); x and y neighbours come from one LDS plane
+// per quantity (phi, h, potential, u*_x, u*_y) published at the start of an
+// iteration, except the y neighbour shared by a thread's two rows, which
+// stays in registers.  The output plane trails the input plane by 3.  One
+// barrier per plane; phi and u* are read once and phi' written once.
+template <typename T, int TXI, int TYT, bool FLUX>
+__global__ void __launch_bounds__(TXI *TYT) k_ch_march3(KParams p, int seg, const T *__restrict__ phi_in,
                                                         const T *__restrict__ u, T *__restrict__ phi_out) {
-  constexpr int R = 4;  // planes of the u* ring
-  __shared__ T xphi[2][TYI][TXI], xh[2][TYI][TXI], xmu[2][TYI][TXI];
-  __shared__ T sux[R][TYI][TXI], suy[R][TYI][TXI], suz[R][TYI][TXI];
+  constexpr int TYI = 2 * TYT;
+  __shared__ T xphi[2][TYI][TXI], xh[2][TYI][TXI], xmu[2][TYI][TXI], xux[2][TYI][TXI], xuy[2][TYI][TXI];
   const int nx = p.nx, ny = p.ny, nz = p.nz;
-  const int cx = threadIdx.x % TXI, cy = threadIdx.x / TXI;
+  const int cx = threadIdx.x % TXI, ty = threadIdx.x / TXI;
+  const int cy0 = 2 * ty, cy1 = 2 * ty + 1;
   const int X0 = blockIdx.x * (TXI - 6), Y0 = blockIdx.y * (TYI - 6);
   const int z0 = blockIdx.z * seg, z1 = min(z0 + seg, nz);
-  const int gx = wrapc(X0 - 3 + cx, nx), gy = wrapc(Y0 - 3 + cy, ny);
-  const bool col_out = cx >= 3 && cx < TXI - 3 && cy >= 3 && cy < TYI - 3 && X0 + cx - 3 < nx && Y0 + cy - 3 < ny;
+  const int gx = wrapc(X0 - 3 + cx, nx);
+  const int gy0 = wrapc(Y0 - 3 + cy0, ny), gy1 = wrapc(Y0 - 3 + cy1, ny);
+  const bool xin = cx >= 3 && cx < TXI - 3 && X0 + cx - 3 < nx;
+  const bool out0 = xin && cy0 >= 3 && cy0 < TYI - 3 && Y0 + cy0 - 3 < ny;
+  const bool out1 = xin && cy1 >= 3 && cy1 < TYI - 3 && Y0 + cy1 - 3 < ny;
   // edge lanes read themselves; their results are never used
   const int cxm = cx > 0 ? cx - 1 : 0, cxp = cx < TXI - 1 ? cx + 1 : TXI - 1;
-  const int cym = cy > 0 ? cy - 1 : 0, cyp = cy < TYI - 1 ? cy + 1 : TYI - 1;
+  const int cym = cy0 > 0 ? cy0 - 1 : 0, cyp = cy1 < TYI - 1 ? cy1 + 1 : TYI - 1;
   const size_t ns = (size_t)p.ns;
   const T *ux_g = u, *uy_g = u + ns, *uz_g = u + 2 * ns;
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
   const int t0 = z0 - 3, t1 = z1 + 3;  // iterations [t0, t1); output plane t - 3
   const bool wide = nz >= 4;
-  const int col = gx + nx * gy;
   const size_t plane = (size_t)nx * ny;
+  const size_t col0 = gx + (size_t)nx * gy0, col1 = gx + (size_t)nx * gy1;
   auto plane_of = [&](int t) { return wide ? wrap1(t, nz) : wrapc(t, nz); };
 
-  // registers: phi planes (t-2, t-1), h planes (t-3, t-2), mu planes (t-4, t-3)
-  T ph2 = T(0), ph1 = T(0), h2 = T(0), h1 = T(0), m2 = T(0), m1 = T(0);
-  size_t g = col + plane * plane_of(t0);
-  T nphi = phi_in[g], nux = ux_g[g], nuy = uy_g[g], nuz = uz_g[g];
-  for (int t = t0; t < t1; t++) {
-    const int par = t & 1;
-    const int slot = (t - t0) & (R - 1);
-    sux[slot][cy][cx] = nux;
-    suy[slot][cy][cx] = nuy;
-    suz[slot][cy][cx] = nuz;
-    xphi[par][cy][cx] = ph1;
-    xh[par][cy][cx] = h1;
-    xmu[par][cy][cx] = m1;
-    const T in = nphi;  // phi plane t
-    if (t + 1 < t1) {
-      g = col + plane * plane_of(t + 1);
-      nphi = phi_in[g];
-      nux = ux_g[g];
-      nuy = uy_g[g];
-      nuz = uz_g[g];
+  // per row r of the pair: phi planes (t-2, t-1), h (t-3, t-2), mu (t-4, t-3),
+  // u*_x, u*_y at plane t-1, u*_z planes (t-2, t-1), and the loaded plane t
+  T ph2[2] = {0, 0}, ph1[2] = {0, 0}, h2[2] = {0, 0}, h1[2] = {0, 0}, m2[2] = {0, 0}, m1[2] = {0, 0};
+  T ux1[2] = {0, 0}, uy1[2] = {0, 0}, uz2[2] = {0, 0}, uz1[2] = {0, 0};
+  // input planes in flight: queue slot k holds plane t0 + k + 2j at its j-th use
+  T qphi[2][2], qux[2][2], quy[2][2], quz[2][2];
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    if (t0 + k < t1) {
+      const size_t pz = plane * plane_of(t0 + k);
+      qphi[k][0] = phi_in[col0 + pz];
+      qux[k][0] = ux_g[col0 + pz];
+      quy[k][0] = uy_g[col0 + pz];
+      quz[k][0] = uz_g[col0 + pz];
+      qphi[k][1] = phi_in[col1 + pz];
+      qux[k][1] = ux_g[col1 + pz];
+      quy[k][1] = uy_g[col1 + pz];
+      quz[k][1] = uz_g[col1 + pz];
+    }
+  }
+  // one iteration: input plane t from queue slot k (parity of the published planes = k)
+  auto iterate = [&](const int t, const int k) {
+    const int par = k;
+    const int cy[2] = {cy0, cy1};
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      xphi[par][cy[r]][cx] = ph1[r];
+      xh[par][cy[r]][cx] = h1[r];
+      xmu[par][cy[r]][cx] = m1[r];
+      xux[par][cy[r]][cx] = ux1[r];
+      xuy[par][cy[r]][cx] = uy1[r];
+    }
+    T in[2], inux[2], inuy[2], inuz[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      in[r] = qphi[k][r];
+      inux[r] = qux[k][r];
+      inuy[r] = quy[k][r];
+      inuz[r] = quz[k][r];
+    }
+    if (t + 2 < t1) {  // refill the slot with plane t + 2
+      const size_t pz = plane * plane_of(t + 2);
+      qphi[k][0] = phi_in[col0 + pz];
+      qux[k][0] = ux_g[col0 + pz];
+      quy[k][0] = uy_g[col0 + pz];
+      quz[k][0] = uz_g[col0 + pz];
+      qphi[k][1] = phi_in[col1 + pz];
+      qux[k][1] = ux_g[col1 + pz];
+      quy[k][1] = uy_g[col1 + pz];
+      quz[k][1] = uz_g[col1 + pz];
     }
     __syncthreads();
-    const int kc = (t - t0 - 1) & (R - 1), kd = (t - t0 - 2) & (R - 1), ku = (t - t0) & (R - 1);
-    // advection half-step at plane t-1
-    const T pc = ph1;
-    const T pw = xphi[par][cy][cxm], pe = xphi[par][cy][cxp];
-    const T ps_ = xphi[par][cym][cx], pn = xphi[par][cyp][cx];
-    const T pd = ph2, pu = in;
-    const T uxc = sux[kc][cy][cx], uxw = sux[kc][cy][cxm], uxe = sux[kc][cy][cxp];
-    const T uyc = suy[kc][cy][cx], uys = suy[kc][cym][cx], uyn = suy[kc][cyp][cx];
-    const T uzc = suz[kc][cy][cx], uzd = suz[kd][cy][cx], uzu = suz[ku][cy][cx];
-    T rhs;
-    if constexpr (!FLUX) {
-      const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
-      const T ty = pc * ((uyn - uys) * T(0.5)) + uyc * (uyc > T(0) ? pc - ps_ : pn - pc);
-      const T tz = pc * ((uzu - uzd) * T(0.5)) + uzc * (uzc > T(0) ? pc - pd : pu - pc);
-      rhs = tx + ty + tz;
-    } else {
-      const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
-      const T vyn = (uyc + uyn) * T(0.5), vys = (uys + uyc) * T(0.5);
-      const T vzu = (uzc + uzu) * T(0.5), vzd = (uzd + uzc) * T(0.5);
-      const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
-      const T ty = (vyn > T(0) ? vyn * pc : vyn * pn) - (vys > T(0) ? vys * ps_ : vys * pc);
-      const T tz = (vzu > T(0) ? vzu * pc : vzu * pu) - (vzd > T(0) ? vzd * pd : vzd * pc);
-      rhs = tx + ty + tz;
+    // y neighbours at the published plane: below row 0 and above row 1 from LDS,
+    // between the two rows from registers
+    const T phs = xphi[par][cym][cx], phn = xphi[par][cyp][cx];
+    const T hs = xh[par][cym][cx], hnb = xh[par][cyp][cx];
+    const T ms = xmu[par][cym][cx], mnb = xmu[par][cyp][cx];
+    const T uys = xuy[par][cym][cx], uyn = xuy[par][cyp][cx];
+    T out[2], hnew[2], mnew[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int y = cy[r];
+      // values of the neighbouring rows (south, north) in this plane
+      const T p_s = r == 0 ? phs : ph1[0], p_n = r == 0 ? ph1[1] : phn;
+      const T h_s = r == 0 ? hs : h1[0], h_n = r == 0 ? h1[1] : hnb;
+      const T m_s = r == 0 ? ms : m1[0], m_n = r == 0 ? m1[1] : mnb;
+      const T uy_s = r == 0 ? uys : uy1[0], uy_n = r == 0 ? uy1[1] : uyn;
+      // advection half-step at plane t-1
+      const T pc = ph1[r];
+      const T pw = xphi[par][y][cxm], pe = xphi[par][y][cxp];
+      const T pd = ph2[r], pu = in[r];
+      const T uxc = ux1[r], uxw = xux[par][y][cxm], uxe = xux[par][y][cxp];
+      const T uyc = uy1[r];
+      const T uzc = uz1[r], uzd = uz2[r], uzu = inuz[r];
+      T rhs;
+      if constexpr (!FLUX) {
+        const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
+        const T ty_ = pc * ((uy_n - uy_s) * T(0.5)) + uyc * (uyc > T(0) ? pc - p_s : p_n - pc);
+        const T tz = pc * ((uzu - uzd) * T(0.5)) + uzc * (uzc > T(0) ? pc - pd : pu - pc);
+        rhs = tx + ty_ + tz;
+      } else {
+        const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
+        const T vyn = (uyc + uy_n) * T(0.5), vys = (uy_s + uyc) * T(0.5);
+        const T vzu = (uzc + uzu) * T(0.5), vzd = (uzd + uzc) * T(0.5);
+        const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
+        const T ty_ = (vyn > T(0) ? vyn * pc : vyn * p_n) - (vys > T(0) ? vys * p_s : vys * pc);
+        const T tz = (vzu > T(0) ? vzu * pc : vzu * pu) - (vzd > T(0) ? vzd * pd : vzd * pc);
+        rhs = tx + ty_ + tz;
+      }
+      hnew[r] = pc - dt * rhs;
+      // diffusion potential at plane t-2
+      const T hc = h1[r];
+      const T Lh = cQ * ((xh[par][y][cxp] + xh[par][y][cxm]) + (h_n + h_s) + (hnew[r] + h2[r])) + cC * hc;
+      mnew[r] = a * hc + b * ph2[r] * ph2[r] * ph2[r] - kappa * Lh;
+      // phi' at plane t-3
+      const T mc = m1[r];
+      const T Lm = cQ * ((xmu[par][y][cxp] + xmu[par][y][cxm]) + (m_n + m_s) + (mnew[r] + m2[r])) + cC * mc;
+      out[r] = h2[r] + dtg * Lm;
     }
-    const T hn = pc - dt * rhs;
-    // diffusion potential at plane t-2
-    const T hc = h1;
-    const T Lh = cQ * ((xh[par][cy][cxp] + xh[par][cy][cxm]) + (xh[par][cyp][cx] + xh[par][cym][cx]) +
-                       (hn + h2)) + cC * hc;
-    const T mn = a * hc + b * ph2 * ph2 * ph2 - kappa * Lh;
-    // phi' at plane t-3
-    const T mc = m1;
-    const T Lm = cQ * ((xmu[par][cy][cxp] + xmu[par][cy][cxm]) + (xmu[par][cyp][cx] + xmu[par][cym][cx]) +
-                       (mn + m2)) + cC * mc;
-    const T out = h2 + dtg * Lm;
-    ph2 = ph1;
-    ph1 = in;
-    h2 = h1;
-    h1 = hn;
-    m2 = m1;
-    m1 = mn;
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      ph2[r] = ph1[r];
+      ph1[r] = in[r];
+      h2[r] = h1[r];
+      h1[r] = hnew[r];
+      m2[r] = m1[r];
+      m1[r] = mnew[r];
+      ux1[r] = inux[r];
+      uy1[r] = inuy[r];
+      uz2[r] = uz1[r];
+      uz1[r] = inuz[r];
+    }
     const int zo = t - 3;
-    if (col_out && zo >= z0 && zo < z1) phi_out[col + plane * zo] = out;
+    if (zo >= z0 && zo < z1) {
+      if (out0) phi_out[col0 + plane * zo] = out[0];
+      if (out1) phi_out[col1 + plane * zo] = out[1];
+    }
+  };
+  // unrolled by two so the queue slot and the parity are static
+  for (int t = t0; t < t1; t += 2) {
+    iterate(t, 0);
+    if (t + 1 < t1) iterate(t + 1, 1);
   }
 }
 
