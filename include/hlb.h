@@ -179,6 +179,9 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
  *                 1 = marching launches (cd_Q = 1 only): in D2Q9 a launch
  *                     marches along y and runs plan[1] substeps; in D3Q19 a
  *                     launch marches along z and runs one substep;
+ *                 2 = fused tiles (D2Q9, cd_Q = 1): a launch runs plan[1]
+ *                     substeps (1, 2, 3 or 5) of plan[2] x plan[2] tiles
+ *                     (16 or 32) in LDS, halo 3 per substep;
  *   plan[1] fuse: substeps per launch, 1..5 (D2Q9), 1 (D3Q19);
  *   plan[2] bw:   D2Q9: columns per block, 64, 128 or 256 (256 with
  *                 HLB_F32_SHIFTED only), bw - 6*fuse >= 16;

@@ -367,6 +367,34 @@ struct Ops {
       else if constexpr (sizeof(T) == 4) march_bw<256>(c, k, M, c->plan.seg, src, dst);
     }
   }
+  template <int M, int TO>
+  static void tile1(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
+    const dim3 grid(ceil_div(c->nx, TO), ceil_div(c->ny, TO));
+    if (k.advection == 1)
+      hipLaunchKernelGGL((k_ch_tile<T, M, TO, true>), grid, dim3(NT), 0, c->stream, k, src, at<T>(c, c->lay.u), dst);
+    else
+      hipLaunchKernelGGL((k_ch_tile<T, M, TO, false>), grid, dim3(NT), 0, c->stream, k, src, at<T>(c, c->lay.u), dst);
+  }
+  template <int TO>
+  static void tile_to(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
+    switch (M) {
+      case 1: tile1<1, TO>(c, k, src, dst); break;
+      case 2: tile1<2, TO>(c, k, src, dst); break;
+      case 3: tile1<3, TO>(c, k, src, dst); break;
+      default:
+        if constexpr (sizeof(T) == 4 || TO == 16) tile1<5, TO>(c, k, src, dst);
+        break;
+    }
+  }
+  // one fused-tile launch of M substeps: phi[phicur] -> phi[1 - phicur]
+  static void tile(hlb_ctx *c, const KParams &k, int M) {
+    if constexpr (L::D == 2) {
+      const T *src = at<T>(c, c->lay.phi[c->phicur]);
+      T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
+      if (c->plan.bw == 16) tile_to<16>(c, k, M, src, dst);
+      else tile_to<32>(c, k, M, src, dst);
+    }
+  }
   static void init(hlb_ctx *c, const KParams &k) {
     const unsigned nb = (unsigned)((c->ns + 255) / 256);
     hipLaunchKernelGGL((k_init<L, T>), dim3(nb), dim3(256), 0, c->stream, k, at<double>(c, c->lay.io),
@@ -448,6 +476,14 @@ void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
         c->phicur = 1 - c->phicur;
         done += M;
       }
+    } else if (c->plan.kind == 2) {
+      for (int done = 0; done < c->m;) {
+        int M = std::min(c->plan.fuse, c->m - done);
+        if (M == 4) M = 3;  // instantiated: 1, 2, 3, 5
+        ops.tile(c, k, M);
+        c->phicur = 1 - c->phicur;
+        done += M;
+      }
     } else {
       for (int s = 0; s < c->m; s++) {
         ops.ch(c, k);
@@ -463,8 +499,27 @@ void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
 // Whether a plan can run this context.
 bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
   if (pl.kind == 0) return true;
+  if (pl.kind == 2) {
+    if (c->lattice != HLB_D2Q9 || c->p.cd_Q != 1.0) {
+      *why = "the fused tile kernel needs D2Q9 and cd_Q = 1";
+      return false;
+    }
+    if (pl.fuse < 1 || pl.fuse > 5 || pl.fuse == 4) {
+      *why = "fused tile: fuse must be 1, 2, 3 or 5";
+      return false;
+    }
+    if (pl.bw != 16 && pl.bw != 32) {
+      *why = "fused tile: bw (tile edge) must be 16 or 32";
+      return false;
+    }
+    if (c->storage == HLB_F64 && pl.bw == 32 && pl.fuse == 5) {
+      *why = "fused tile: 32-site tiles of 5 substeps need float storage (LDS size)";
+      return false;
+    }
+    return true;
+  }
   if (pl.kind != 1) {
-    *why = "plan kind must be 0 or 1";
+    *why = "plan kind must be 0, 1 or 2";
     return false;
   }
   if (c->p.cd_Q != 1.0) {
@@ -842,7 +897,12 @@ hlb_status hlb_reduce(hlb_ctx *c, hlb_stats *out) {
 
 const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
   if (!c || cls < 0 || cls > 1) return "";
-  if (cls == 1 && c->plan.kind == 1) {
+  if (cls == 1 && c->plan.kind == 2) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "hlb::k_ch_tile<%s, %d, %d>", c->storage == HLB_F64 ? "double" : "float",
+             std::min(c->plan.fuse, c->m), c->plan.bw);
+    const_cast<hlb_ctx *>(c)->names[1] = buf;
+  } else if (cls == 1 && c->plan.kind == 1) {
     hlb_ctx *mc = const_cast<hlb_ctx *>(c);
     char buf[160];
     if (c->lattice == HLB_D3Q19)
@@ -893,6 +953,12 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
       }
   }
   if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
+    for (int fuse : {1, 2, 3, 5})
+      for (int to : {16, 32}) {
+        ChPlan pl{2, std::min(fuse, c->m == 4 ? 3 : c->m), to, 0};
+        std::string why;
+        if (fuse <= c->m && plan_valid(c, pl, &why)) cand.push_back(pl);
+      }
     for (int fuse = 1; fuse <= std::min(c->m, 5); fuse++)
       for (int bw : {64, 128, 256})
         for (int seg : {8, 16, 32, 64, 128, 256}) {
@@ -910,12 +976,14 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   ChPlan best_pl = saved;
   for (const ChPlan &pl : cand) {
     c->plan = pl;
-    const int per = pl.kind == 1 ? std::min(pl.fuse, c->m) : 1;  // substeps per timed launch
+    int per = pl.kind == 0 ? 1 : std::min(pl.fuse, c->m);  // substeps per timed launch
+    if (pl.kind == 2 && per == 4) per = 3;
     float ms = 0;
     for (int rep = 0; rep < 4; rep++) {
       (void)hipEventRecord(e0, c->stream);
       dispatch(c, [&](auto ops) {
         if (pl.kind == 1) ops.march(c, k, per);
+        else if (pl.kind == 2) ops.tile(c, k, per);
         else ops.ch(c, k);
       });
       (void)hipEventRecord(e1, c->stream);

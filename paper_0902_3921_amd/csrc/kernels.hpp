@@ -607,6 +607,88 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
   }
 }
 
+// M convection-diffusion substeps of one TO x TO tile in a single launch
+// (2D, standard 5-point Laplacian).  phi and u* are staged once with a halo
+// of 3M; substep s then works on a region that shrinks by 3 on every side
+// (its output region is the next substep's input), entirely in LDS: h with
+// a halo of 2, the diffusion potential with a halo of 1, then phi^{s+1},
+// written over phi^s in place (the last phase reads only h and the
+// potential).  Global traffic: phi and u* read once, phi' written once.
+template <typename T, int M, int TO, bool FLUX>
+__global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
+                                                T *__restrict__ phi_out) {
+  constexpr int H = 3 * M;
+  constexpr int L0 = TO + 2 * H;  // staged region edge
+  __shared__ T sphi[1][L0][L0], sux[1][L0][L0], suy[1][L0][L0];
+  __shared__ T sh[L0 - 2][L0 - 2], smu[L0 - 4][L0 - 4];
+  const int x0 = blockIdx.x * TO, y0 = blockIdx.y * TO;
+  const size_t ns = (size_t)p.ns;
+  {
+    TileLoad<2, T, L0, L0, 1> lphi, lux, luy;
+    lphi.issue(phi_in, p, x0 - H, y0 - H, 0);
+    lux.issue(u, p, x0 - H, y0 - H, 0);
+    luy.issue(u + ns, p, x0 - H, y0 - H, 0);
+    lphi.commit(sphi);
+    lux.commit(sux);
+    luy.commit(suy);
+  }
+  __syncthreads();
+  const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
+  const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
+
+#pragma unroll
+  for (int s = 0; s < M; s++) {
+    // input region of substep s: [3s, L0 - 3s) on both axes of the staged box
+    const int lo = 3 * s;
+    const int LH = L0 - 6 * s - 2;  // h region edge, origin lo + 1
+    for (int i = threadIdx.x; i < LH * LH; i += NT) {
+      const int y = lo + 1 + i / LH, x = lo + 1 + i % LH;
+      const T pc = sphi[0][y][x];
+      const T pw = sphi[0][y][x - 1], pe = sphi[0][y][x + 1];
+      const T pdn = sphi[0][y - 1][x], pup = sphi[0][y + 1][x];
+      const T uxc = sux[0][y][x], uxw = sux[0][y][x - 1], uxe = sux[0][y][x + 1];
+      const T uyc = suy[0][y][x], uyd = suy[0][y - 1][x], uyu = suy[0][y + 1][x];
+      T rhs;
+      if constexpr (!FLUX) {
+        const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
+        const T ty = pc * ((uyu - uyd) * T(0.5)) + uyc * (uyc > T(0) ? pc - pdn : pup - pc);
+        rhs = tx + ty;
+      } else {
+        const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
+        const T vyu = (uyc + uyu) * T(0.5), vyd = (uyd + uyc) * T(0.5);
+        const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
+        const T ty = (vyu > T(0) ? vyu * pc : vyu * pup) - (vyd > T(0) ? vyd * pdn : vyd * pc);
+        rhs = tx + ty;
+      }
+      sh[y - 1][x - 1] = pc - dt * rhs;
+    }
+    __syncthreads();
+    const int LM = LH - 2;  // potential region edge, origin lo + 2
+    for (int i = threadIdx.x; i < LM * LM; i += NT) {
+      const int y = lo + 2 + i / LM, x = lo + 2 + i % LM;
+      const int hy = y - 1, hx = x - 1;
+      const T hc = sh[hy][hx];
+      const T Lh = cQ * ((sh[hy][hx + 1] + sh[hy][hx - 1]) + (sh[hy + 1][hx] + sh[hy - 1][hx])) + cC * hc;
+      const T ph = sphi[0][y][x];
+      smu[y - 2][x - 2] = a * hc + b * ph * ph * ph - kappa * Lh;
+    }
+    __syncthreads();
+    const int LO = LM - 2;  // output region edge, origin lo + 3
+    for (int i = threadIdx.x; i < LO * LO; i += NT) {
+      const int y = lo + 3 + i / LO, x = lo + 3 + i % LO;
+      const int my = y - 2, mx = x - 2;
+      const T Lm = cQ * ((smu[my][mx + 1] + smu[my][mx - 1]) + (smu[my + 1][mx] + smu[my - 1][mx])) + cC * smu[my][mx];
+      sphi[0][y][x] = sh[y - 1][x - 1] + dtg * Lm;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < TO * TO; i += NT) {
+    const int ty = i / TO, tx = i % TO;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x < p.nx && y < p.ny) phi_out[x + p.nx * y] = sphi[0][H + ty][H + tx];
+  }
+}
+
 // One convection-diffusion substep in 3D (standard 7-point Laplacian),
 // marching along z.  A block of TXI x TYT threads owns TXI x 2 TYT (x, y)
 // columns, two neighbouring rows per thread, and walks the z planes of its

@@ -245,15 +245,16 @@ def test_nonfinite_state_is_reported(hlb):
 
 
 @pytest.mark.parametrize("plan", [(0, 1, 128, 64), (1, 5, 64, 7), (1, 5, 128, 16), (1, 5, 256, 40),
-                                  (1, 2, 64, 9), (1, 3, 128, 100), (1, 1, 64, 1)])
+                                  (1, 2, 64, 9), (1, 3, 128, 100), (1, 1, 64, 1),
+                                  (2, 5, 32, 1), (2, 5, 16, 0), (2, 2, 32, 0), (2, 3, 16, 1), (2, 1, 16, 0)])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_substep_plans_agree(hlb, plan, storage):
     """Every execution plan of the convection-diffusion substeps (one launch
     per substep, or fused y-marching launches of several substeps with
     various block shapes) computes the same step: ragged 150 x 83 lattice,
     m = 5 split into fused launches of plan[1] substeps."""
-    if storage == "f64" and plan[2] == 256:
-        pytest.skip("bw = 256 needs float storage")
+    if storage == "f64" and (plan[2] == 256 or plan[:3] == (2, 5, 32)):
+        pytest.skip("needs float storage (LDS size)")
     shape = (83, 150)
     phi = _drop(shape, 20, BASE) + synth.spinodal(shape, seed=5, amp=0.02)
     u0 = np.zeros((2,) + shape)
@@ -272,18 +273,20 @@ def test_fused_plan_on_lattices_smaller_than_the_halo(hlb):
     """The fused kernel's strip and march wrap around lattices narrower or
     shorter than its halo (3 rows per fused substep)."""
     for shape in [(7, 9), (40, 5), (3, 100)]:
-        phi = synth.spinodal(shape, seed=sum(shape), amp=0.3)
-        gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=0.3, Q=2.5)
-        gpu.set_plan(1, 5, 64, 4)
-        gpu.step(6)
-        ora.step(6)
-        d = _maxdiff(gpu, ora)
-        assert max(d.values()) < 1e-13, (shape, d)
+        for plan in [(1, 5, 64, 4), (2, 5, 16, 0)]:
+            phi = synth.spinodal(shape, seed=sum(shape), amp=0.3)
+            gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=0.3, Q=2.5)
+            gpu.set_plan(*plan)
+            gpu.step(6)
+            ora.step(6)
+            d = _maxdiff(gpu, ora)
+            assert max(d.values()) < 1e-13, (shape, plan, d)
 
 
 def test_invalid_plans_rejected(hlb):
     gpu = hlb.Sim((32, 32), "f64", **BASE)
-    for bad in [(2, 1, 64, 8), (1, 6, 128, 8), (1, 5, 96, 8), (1, 5, 256, 8), (1, 1, 64, 0), (1, 5, 32, 8)]:
+    for bad in [(3, 1, 64, 8), (1, 6, 128, 8), (1, 5, 96, 8), (1, 5, 256, 8), (1, 1, 64, 0), (1, 5, 32, 8),
+                (2, 4, 16, 0), (2, 5, 64, 0), (2, 5, 32, 0)]:
         with pytest.raises(hlb.HlbError) as e:
             gpu.set_plan(*bad)
         assert e.value.status == hlb.HLB_EINVAL
