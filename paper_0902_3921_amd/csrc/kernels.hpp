@@ -105,6 +105,23 @@ constexpr int NT = 256;
 // in flight into registers, commit() writes them to LDS.  Issuing every load
 // of a kernel (tiles and populations) before the first use keeps the memory
 // pipeline full instead of paying one latency per loop iteration.
+// Block coordinates with an XCD-aware order.  The hardware hands workgroup i
+// (linear id, x fastest) to XCD i mod 8; remapping so that each XCD owns a
+// contiguous range of tiles keeps neighbouring tiles, whose halos overlap,
+// in the same L2.
+__device__ __forceinline__ void tile_coords(int &bx, int &by, int &bz) {
+  constexpr int NXCD = 8;
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nblk = gx * gy * gridDim.z;
+  const int bid = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int q = nblk / NXCD, r = nblk % NXCD;
+  const int xcd = bid % NXCD, pos = bid / NXCD;
+  const int lid = xcd * q + min(xcd, r) + pos;
+  bx = lid % gx;
+  by = (lid / gx) % gy;
+  bz = lid / (gx * gy);
+}
+
 template <int D, typename T, int PX, int PY, int PZ>
 struct TileLoad {
   static constexpr int N = PX * PY * PZ;
@@ -342,7 +359,9 @@ __global__ void __launch_bounds__(NT) k_lb(KParams p, const T *__restrict__ gin,
   constexpr int NSITE = (TX * TY * TZ + NT - 1) / NT;  // sites per thread
   using FT = ForceTile<D, T, TX, TY, TZ>;
   __shared__ FT tile;
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * TZ : 0;
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int x0 = bx * TX, y0 = by * TY, z0 = D == 3 ? bz * TZ : 0;
 
   // all global loads first: this thread's populations, then the phi tile
   T f[NSITE][L::Q];
@@ -408,7 +427,9 @@ __global__ void __launch_bounds__(NT) k_ch(KParams p, const T *__restrict__ phi_
   __shared__ T su[D][PZ][PY][PX];
   __shared__ T sh[HZ][HY][HX];
   __shared__ T smu[MZ][MY][MX];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * TZ : 0;
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int x0 = bx * TX, y0 = by * TY, z0 = D == 3 ? bz * TZ : 0;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const size_t ns = (size_t)p.ns;
   {
@@ -499,8 +520,10 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
   __shared__ T sux[R][BW], suy[R][BW];
   const int nx = p.nx, ny = p.ny;
   const int c = threadIdx.x;
-  const int X0 = blockIdx.x * (BW - 6 * M);
-  const int y0 = blockIdx.y * seg, y1 = min(y0 + seg, ny);
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int X0 = bx * (BW - 6 * M);
+  const int y0 = by * seg, y1 = min(y0 + seg, ny);
   const int gx = wrapc(X0 - 3 * M + c, nx);
   const bool col_out = c >= 3 * M && c < BW - 3 * M && X0 + c - 3 * M < nx;
   const int cm = c > 0 ? c - 1 : 0, cp = c < BW - 1 ? c + 1 : BW - 1;  // edge lanes: values unused
@@ -621,7 +644,9 @@ __global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__
   constexpr int L0 = TO + 2 * H;  // staged region edge
   __shared__ T sphi[1][L0][L0], sux[1][L0][L0], suy[1][L0][L0];
   __shared__ T sh[L0 - 2][L0 - 2], smu[L0 - 4][L0 - 4];
-  const int x0 = blockIdx.x * TO, y0 = blockIdx.y * TO;
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int x0 = bx * TO, y0 = by * TO;
   const size_t ns = (size_t)p.ns;
   {
     TileLoad<2, T, L0, L0, 1> lphi, lux, luy;
@@ -707,8 +732,10 @@ __global__ void __launch_bounds__(TXI *TYT) k_ch_march3(KParams p, int seg, cons
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const int cx = threadIdx.x % TXI, ty = threadIdx.x / TXI;
   const int cy0 = 2 * ty, cy1 = 2 * ty + 1;
-  const int X0 = blockIdx.x * (TXI - 6), Y0 = blockIdx.y * (TYI - 6);
-  const int z0 = blockIdx.z * seg, z1 = min(z0 + seg, nz);
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int X0 = bx * (TXI - 6), Y0 = by * (TYI - 6);
+  const int z0 = bz * seg, z1 = min(z0 + seg, nz);
   const int gx = wrapc(X0 - 3 + cx, nx);
   const int gy0 = wrapc(Y0 - 3 + cy0, ny), gy1 = wrapc(Y0 - 3 + cy1, ny);
   const bool xin = cx >= 3 && cx < TXI - 3 && X0 + cx - 3 < nx;
