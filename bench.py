@@ -23,6 +23,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# rocprofv3 counter scale, from a 1 GiB device copy (1 GiB read, 1 GiB written)
+# that reads FETCH_SIZE = 524,300 KiB and WRITE_SIZE = 1,048,576 KiB
+FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
 
 BASE = dict(a=-0.1, b=0.1, kappa=0.1, tau=1.0, gamma=1.0)
 PAPER_STENCIL = dict(N=0.3, Q=2.5)
@@ -64,7 +67,7 @@ def make_inputs(name, shape):
     return synth.spinodal(shape, seed=0)
 
 
-def run_gpu(name, steps, warmup):
+def run_gpu(name, steps, warmup, plan=None):
     import torch
 
     from paper_0902_3921_amd import hlb
@@ -94,7 +97,7 @@ def run_gpu(name, steps, warmup):
         stats = sim.reduce(raise_on_error=False)
         return sim, t1 - t0, stats
 
-    sim, secs, stats = timed(kw)
+    sim, secs, stats = timed(kw, plan)
     m = sim.m
     plan = sim.plan
     # per-kernel durations from HIP events on the library's stream
@@ -133,6 +136,35 @@ def run_gpu(name, steps, warmup):
     }
 
 
+def measured_traffic(name, kernel_name):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 summary of
+    this workload (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the
+    copy calibration), or None if the summary is missing, does not list the
+    kernel, or was taken on different library sources."""
+    from paper_0902_3921_amd import build
+
+    path = os.path.join(ROOT, "profiles", f"{name}.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    if f"library source hash: {build.source_hash()}" not in text:
+        return None
+    prefix = kernel_name.split("<")[0] + "<" + kernel_name.split("<")[1].split(",")[0] if "<" in kernel_name else kernel_name
+    best = None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 4 and cells[0].startswith(prefix):
+            try:
+                fetch, write = float(cells[2]), float(cells[3])
+            except ValueError:
+                continue
+            if best is None or int(cells[1]) > best[0]:
+                best = (int(cells[1]), fetch, write)
+    if best is None:
+        return None
+    return best[1] * 1024 * FETCH_SCALE + best[2] * 1024 * WRITE_SCALE
+
+
 def run_cpu_baseline(name, budget_s=15.0):
     """The FP64 oracle on a bounded number of steps of the same workload."""
     from oracle import orc
@@ -164,6 +196,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="d2q9_spinodal_1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plan", default=None,
+                    help="substep plan kind,fuse,bw,seg to use instead of autotuning (e.g. for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a device copy of this many MiB (for the HBM counter scale)")
     args = ap.parse_args()
@@ -179,7 +213,8 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
 
-    r = run_gpu(args.workload, args.steps, args.warmup)
+    plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
+    r = run_gpu(args.workload, args.steps, args.warmup, plan)
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -211,8 +246,9 @@ def main():
                    "stencil": "N=0.3, Q=2.5" if r["d"] == 2 else "N=1/6, Q=1/3",
                    "params": "a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1", "seed": 0},
         "roofline": {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": None, "kernel": kd["name"],
-                     "bytes_per_lu": kd["bytes_per_lu"]},
+                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, kd["name"]),
+                     "kernel": kd["name"], "bytes_per_lu": kd["bytes_per_lu"],
+                     "algorithmic_bytes_per_launch": kd["bytes_per_lu"] * r["ns"]},
         "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
         "mlups_standard_stencil": r["mlups_standard"],
         "kernels": r["kernels"],

@@ -34,6 +34,17 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def source_hash() -> str:
+    """SHA-256 of the library sources (kernels, host code, C header)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for path in sorted(SOURCES + HEADERS):
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def stale() -> bool:
     if not os.path.exists(LIB):
         return True

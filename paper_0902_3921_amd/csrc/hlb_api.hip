@@ -298,6 +298,7 @@ dim3 tile_grid(const hlb_ctx *c, const int t[3]) {
 // Per-(lattice, storage) launches.
 template <class L, typename T>
 struct Ops {
+  using Type = T;
   using TL = Tiles<L, T>;
   static constexpr int LB0 = TL::LB[0], LB1 = TL::LB[1], LB2 = TL::LB[2];
   static constexpr int CH0 = TL::CH[0], CH1 = TL::CH[1], CH2 = TL::CH[2];
@@ -308,9 +309,7 @@ struct Ops {
     hipLaunchKernelGGL((k_lb<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k, gin, gout,
                        at<T>(c, c->lay.phi[c->phicur]), at<T>(c, c->lay.u));
   }
-  static void ch(hlb_ctx *c, const KParams &k) {
-    const T *src = at<T>(c, c->lay.phi[c->phicur]);
-    T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
+  static void ch(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
     if (c->p.cd_Q == 1.0)
       hipLaunchKernelGGL((k_ch<L, T, CH0, CH1, CH2, true>), tile_grid(c, TL::CH), dim3(256), 0, c->stream, k, src,
                          at<T>(c, c->lay.u), dst);
@@ -350,18 +349,14 @@ struct Ops {
       hipLaunchKernelGGL((k_ch_march3<T, TXI, TYT, false>), grid, dim3(TXI * TYT), 0, c->stream, k, c->plan.seg,
                          src, at<T>(c, c->lay.u), dst);
   }
-  static void march(hlb_ctx *c, const KParams &k, int M) {
+  static void march(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
     if constexpr (L::D == 3) {
       (void)M;
-      const T *src = at<T>(c, c->lay.phi[c->phicur]);
-      T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
       if (c->plan.bw == 256) march3_1<16, 16>(c, k, src, dst);
       else if (c->plan.bw == 512) march3_1<32, 16>(c, k, src, dst);
       else if constexpr (sizeof(T) == 4) march3_1<64, 16>(c, k, src, dst);
     }
     if constexpr (L::D == 2) {
-      const T *src = at<T>(c, c->lay.phi[c->phicur]);
-      T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
       if (c->plan.bw == 64) march_bw<64>(c, k, M, c->plan.seg, src, dst);
       else if (c->plan.bw == 128) march_bw<128>(c, k, M, c->plan.seg, src, dst);
       else if constexpr (sizeof(T) == 4) march_bw<256>(c, k, M, c->plan.seg, src, dst);
@@ -386,14 +381,47 @@ struct Ops {
         break;
     }
   }
-  // one fused-tile launch of M substeps: phi[phicur] -> phi[1 - phicur]
-  static void tile(hlb_ctx *c, const KParams &k, int M) {
+  // one fused-tile launch of M substeps
+  static void tile(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
     if constexpr (L::D == 2) {
-      const T *src = at<T>(c, c->lay.phi[c->phicur]);
-      T *dst = at<T>(c, c->lay.phi[1 - c->phicur]);
       if (c->plan.bw == 16) tile_to<16>(c, k, M, src, dst);
       else tile_to<32>(c, k, M, src, dst);
     }
+  }
+  // The m substeps of one step with the context's plan: the first launch reads
+  // `in`, launches alternate between writing b0 and b1.  Returns the number of
+  // launches (the result is in b0 if it is odd, else in b1).
+  static int substeps(hlb_ctx *c, const KParams &k, const T *in, T *b0, T *b1) {
+    const T *src = in;
+    T *dst = b0;
+    int n = 0;
+    auto advance = [&]() {
+      src = dst;
+      dst = dst == b0 ? b1 : b0;
+      n++;
+    };
+    if (c->plan.kind == 1) {
+      for (int done = 0; done < c->m;) {
+        const int M = std::min(c->plan.fuse, c->m - done);
+        march(c, k, M, src, dst);
+        advance();
+        done += M;
+      }
+    } else if (c->plan.kind == 2) {
+      for (int done = 0; done < c->m;) {
+        int M = std::min(c->plan.fuse, c->m - done);
+        if (M == 4) M = 3;  // instantiated: 1, 2, 3, 5
+        tile(c, k, M, src, dst);
+        advance();
+        done += M;
+      }
+    } else {
+      for (int s = 0; s < c->m; s++) {
+        ch(c, k, src, dst);
+        advance();
+      }
+    }
+    return n;
   }
   static void init(hlb_ctx *c, const KParams &k) {
     const unsigned nb = (unsigned)((c->ns + 255) / 256);
@@ -468,28 +496,10 @@ void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[0], c->stream);
     ops.lb(c, k);
     if (ev) (void)hipEventRecord(ev[1], c->stream);
-    if (c->plan.kind == 1) {
-      // substeps fused c->plan.fuse at a time, each launch with dt = 1/m
-      for (int done = 0; done < c->m;) {
-        const int M = std::min(c->plan.fuse, c->m - done);
-        ops.march(c, k, M);
-        c->phicur = 1 - c->phicur;
-        done += M;
-      }
-    } else if (c->plan.kind == 2) {
-      for (int done = 0; done < c->m;) {
-        int M = std::min(c->plan.fuse, c->m - done);
-        if (M == 4) M = 3;  // instantiated: 1, 2, 3, 5
-        ops.tile(c, k, M);
-        c->phicur = 1 - c->phicur;
-        done += M;
-      }
-    } else {
-      for (int s = 0; s < c->m; s++) {
-        ops.ch(c, k);
-        c->phicur = 1 - c->phicur;
-      }
-    }
+    using T = typename decltype(ops)::Type;
+    T *cur = at<T>(c, c->lay.phi[c->phicur]), *spare = at<T>(c, c->lay.phi[1 - c->phicur]);
+    const int n = ops.substeps(c, k, cur, spare, cur);
+    if (n % 2 == 1) c->phicur = 1 - c->phicur;
     if (ev) (void)hipEventRecord(ev[2], c->stream);
   });
   c->gcur = 1 - c->gcur;
@@ -940,8 +950,8 @@ hlb_status hlb_get_plan(const hlb_ctx *c, int plan[4]) {
 hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   hlb_status s = usable(c);
   if (s != HLB_OK) return s;
-  // candidate plans, each timed on the convection-diffusion launch that reads
-  // the current phi and writes the spare buffer, so the state is unchanged
+  // candidate plans, each timed on all the substeps of a step, reading the
+  // current phi and writing scratch buffers, so the state is unchanged
   std::vector<ChPlan> cand;
   cand.push_back(ChPlan{0, 1, 128, 64});
   if (c->lattice == HLB_D3Q19 && c->p.cd_Q == 1.0) {
@@ -976,15 +986,15 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   ChPlan best_pl = saved;
   for (const ChPlan &pl : cand) {
     c->plan = pl;
-    int per = pl.kind == 0 ? 1 : std::min(pl.fuse, c->m);  // substeps per timed launch
-    if (pl.kind == 2 && per == 4) per = 3;
-    float ms = 0;
+    float tmin = 1e30f;
     for (int rep = 0; rep < 4; rep++) {
       (void)hipEventRecord(e0, c->stream);
+      // all substeps of a step, from the current phi into two scratch buffers
+      // in the staging area (the state is not touched)
       dispatch(c, [&](auto ops) {
-        if (pl.kind == 1) ops.march(c, k, per);
-        else if (pl.kind == 2) ops.tile(c, k, per);
-        else ops.ch(c, k);
+        using T = typename decltype(ops)::Type;
+        T *scratch = at<T>(c, c->lay.io);
+        ops.substeps(c, k, at<T>(c, c->lay.phi[c->phicur]), scratch, scratch + c->ns);
       });
       (void)hipEventRecord(e1, c->stream);
       s = launch_check(c, "autotune launch");
@@ -992,10 +1002,10 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
       if (s != HLB_OK) break;
       float t = 0;
       (void)hipEventElapsedTime(&t, e0, e1);
-      if (rep > 0) ms += t;  // first launch warms up
+      if (rep > 0) tmin = std::min(tmin, t);  // the first run warms up
     }
     if (s != HLB_OK) break;
-    const double us_per_substep = ms / 3.0 * 1e3 / per;
+    const double us_per_substep = tmin * 1e3 / c->m;
     if (us_per_substep < best) {
       best = us_per_substep;
       best_pl = pl;
