@@ -120,8 +120,11 @@ def run_gpu(name, steps, warmup, plan=None):
         achieved = lb_b * ns / t_lb / 1e9
         kname, kbytes = names[0], lb_b
     else:
+        # a fused plan may end the step with a shorter launch (e.g. 2 + 2 + 1
+        # substeps); the figure is the class average over the step's launches
         achieved = ch_b * ns / t_ch / 1e9
-        kname, kbytes = names[1], ch_b
+        kname = names[1] + (f" (class average over {ch_launches} launches per step)" if ch_launches > 1 else "")
+        kbytes = ch_b
     mlups = ns * steps / secs / 1e6
     return {
         "shape": shape, "storage": storage, "desc": desc, "m": m, "ns": ns, "secs": secs,
@@ -149,20 +152,20 @@ def measured_traffic(name, kernel_name):
     text = open(path).read()
     if f"library source hash: {build.source_hash()}" not in text:
         return None
+    # kernels of the same template and storage type (a fused plan mixes launch
+    # lengths); dispatch-weighted average per launch
     prefix = kernel_name.split("<")[0] + "<" + kernel_name.split("<")[1].split(",")[0] if "<" in kernel_name else kernel_name
-    best = None
+    total, count = 0.0, 0
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if len(cells) == 4 and cells[0].startswith(prefix):
             try:
-                fetch, write = float(cells[2]), float(cells[3])
+                n, fetch, write = int(cells[1]), float(cells[2]), float(cells[3])
             except ValueError:
                 continue
-            if best is None or int(cells[1]) > best[0]:
-                best = (int(cells[1]), fetch, write)
-    if best is None:
-        return None
-    return best[1] * 1024 * FETCH_SCALE + best[2] * 1024 * WRITE_SCALE
+            total += n * (fetch * 1024 * FETCH_SCALE + write * 1024 * WRITE_SCALE)
+            count += n
+    return total / count if count else None
 
 
 def run_cpu_baseline(name, budget_s=15.0):
