@@ -41,7 +41,36 @@ WORKLOADS = {
                           "D2Q9 drop R=20 128x128 periodic, FP64"),
     "d3q19_spinodal_256": ((256, 256, 256), "f32", dict(BASE, N=1 / 6, Q=1 / 3),
                            "D3Q19 spinodal 256^3 periodic, FP32 shifted populations"),
+    # shape None: a batch of independent simulations (batch_workload)
+    "d2q9_batch_512": (None, "f32", dict(BASE, **PAPER_STENCIL),
+                       "512 independent D2Q9 drop/slab simulations, L ~ U{64..256}, kappa ~ U(0.05, 0.2), "
+                       "tau ~ U(0.6, 1.5), FP32 shifted populations, one batch"),
 }
+
+
+def batch_workload(nsim=512, seed=0):
+    """The batched workload: specs from synth.batch_specs (square lattices of
+    side L ~ U{64..256}, kappa ~ U(0.05, 0.2), tau ~ U(0.6, 1.5), a drop of
+    radius ~ U(8, L/4) or a slab with two flat interfaces), a = -0.1,
+    b = 0.1, Gamma = 1, the paper's stencil N = 0.3, Q = 2.5, and the
+    equilibrium tanh profile of amplitude sqrt(-a/b) = 1 and width
+    sqrt(-2 kappa/a).  Returns (specs, params, phis)."""
+    import numpy as np
+
+    import synth
+
+    specs = synth.batch_specs(nsim, seed)
+    params, phis = [], []
+    for s in specs:
+        p = dict(BASE, kappa=s["kappa"], tau=s["tau"], **PAPER_STENCIL)
+        w = np.sqrt(-2 * s["kappa"] / p["a"])
+        if s["kind"] == "drop":
+            phi = synth.drop(s["shape"], s["radius"], 1.0, w, center=s["center"])
+        else:
+            phi = synth.slab(s["shape"], s["x0"], s["x1"], 1.0, w, axis=s["axis"])
+        params.append(p)
+        phis.append(phi)
+    return specs, params, phis
 
 
 def algorithmic_bytes(d: int, q: int, es: int):
@@ -139,6 +168,64 @@ def run_gpu(name, steps, warmup, plan=None):
     }
 
 
+def run_gpu_batch(name, steps, warmup, plan=None):
+    import torch
+
+    from paper_0902_3921_amd import hlb
+
+    _, storage, _, desc = WORKLOADS[name]
+    specs, params, phis = batch_workload()
+    shapes = [s["shape"] for s in specs]
+    es = 8 if storage == "f64" else 4
+    batch = hlb.Batch(shapes, params, storage)
+    for i, phi in enumerate(phis):
+        batch.init(i, phi)
+    if plan is None:
+        batch.autotune()
+    else:
+        batch.set_plan(*plan)
+    batch.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batch.step(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    ms = batch.m
+    ns = [s[0] * s[1] for s in shapes]
+    total = sum(ns)
+    sub_sites = sum(n * m for n, m in zip(ns, ms))  # substep site updates per step
+    nprof = max(10, min(100, steps))
+    ms_lb, ms_ch = batch.step_timed(nprof)
+    stats = [batch.reduce(i, raise_on_error=False) for i in range(len(shapes))]
+    tile_plan = batch.plan
+    batch.close()
+    lb_b, ch_b, step_b = algorithmic_bytes(2, 9, es)
+    t_lb = ms_lb / nprof * 1e-3                 # s per collide-and-stream launch
+    t_ch_step = ms_ch / nprof * 1e-3            # s of substep launches per step
+    max_m = max(ms)
+    t_ch = t_ch_step / max_m                    # s per substep launch (average)
+    lb_gbs = lb_b * total / t_lb / 1e9
+    ch_gbs = ch_b * sub_sites / t_ch_step / 1e9  # bytes of all substeps of a step over their time
+    dominant = "lb" if t_lb > t_ch_step else "ch"
+    lbname = f"hlb::k_lb_batch<float, {tile_plan[0]}, {tile_plan[1]}>"
+    chname = f"hlb::k_ch_batch<float, {tile_plan[2]}, {tile_plan[3]}, true>"
+    kd = ({"name": lbname, "bytes_per_lu": lb_b, "gbs": lb_gbs, "units": total} if dominant == "lb" else
+          {"name": chname + f" (class average over {max_m} launches per step)", "bytes_per_lu": ch_b,
+           "gbs": ch_gbs, "units": sub_sites / max_m})
+    return {
+        "shape": None, "storage": storage, "desc": desc, "m": f"{min(ms)}..{max_m} (mean {sub_sites / total:.2f})",
+        "ns": total, "secs": secs, "mlups": total * steps / secs / 1e6, "mlups_standard": None,
+        "stats": {"finite": all(s["finite"] for s in stats), "mass": sum(s["mass"] for s in stats),
+                  "umax": max(s["umax"] for s in stats)},
+        "plan": tile_plan,
+        "kernels": {"lb": {"name": lbname, "us_per_launch": t_lb * 1e6, "bytes_per_lu": lb_b, "gbs": lb_gbs},
+                    "ch": {"name": chname, "us_per_launch": t_ch * 1e6, "launches_per_step": max_m,
+                           "substep_site_updates_per_step": sub_sites, "bytes_per_lu": ch_b, "gbs": ch_gbs}},
+        "dominant": kd, "step_min_bytes_per_lu": step_b, "q": 9, "d": 2, "es": es,
+        "nsim": len(shapes), "sites": total,
+    }
+
+
 def measured_traffic(name, kernel_name):
     """HBM bytes per launch of a kernel from the committed rocprofv3 summary of
     this workload (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the
@@ -175,6 +262,23 @@ def run_cpu_baseline(name, budget_s=15.0):
     shape, storage, kw, desc = WORKLOADS[name]
     from paper_0902_3921_amd import hlb
 
+    if shape is None:
+        # simulations of the batch in order, 5 steps each, until the budget is spent
+        specs, params, phis = batch_workload()
+        sites, secs, nsim = 0, 0.0, 0
+        for s, p, phi in zip(specs, params, phis):
+            o = orc.Oracle(s["shape"], m=hlb.check_params(0, **p), **p).init(phi)
+            o.step(1)
+            t0 = time.perf_counter()
+            o.step(5)
+            secs += time.perf_counter() - t0
+            sites += 5 * phi.size
+            nsim += 1
+            if secs > budget_s:
+                break
+        return {"value": sites / secs / 1e6, "unit": "MLUPS", "cores": orc.threads(), "kind": "oracle",
+                "sample": f"5 steps (after 1 untimed step) of each of the first {nsim} simulations of the "
+                          f"{desc} workload, one after another (FP64 oracle)"}
     m = hlb.check_params(0 if len(shape) == 2 else 1, **kw)
     phi0 = make_inputs(name, shape)
     ns = 1
@@ -217,7 +321,8 @@ def main():
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
 
     plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
-    r = run_gpu(args.workload, args.steps, args.warmup, plan)
+    batched = WORKLOADS[args.workload][0] is None
+    r = (run_gpu_batch if batched else run_gpu)(args.workload, args.steps, args.warmup, plan)
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -244,14 +349,18 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if r["storage"] == "f32" else "f64",
         "data": "synthetic",
-        "config": {"workload": r["desc"], "lattice": "D2Q9" if r["d"] == 2 else "D3Q19",
-                   "shape": list(r["shape"]), "m": r["m"], "substep_plan": list(r["plan"]),
-                   "stencil": "N=0.3, Q=2.5" if r["d"] == 2 else "N=1/6, Q=1/3",
-                   "params": "a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1", "seed": 0},
+        "config": ({"workload": r["desc"], "lattice": "D2Q9", "nsim": r["nsim"], "sites": r["sites"],
+                    "m": r["m"], "tile_plan": list(r["plan"]), "stencil": "N=0.3, Q=2.5",
+                    "params": "a=-0.1 b=0.1 Gamma=1, kappa and tau per simulation", "seed": 0}
+                   if batched else
+                   {"workload": r["desc"], "lattice": "D2Q9" if r["d"] == 2 else "D3Q19",
+                    "shape": list(r["shape"]), "m": r["m"], "substep_plan": list(r["plan"]),
+                    "stencil": "N=0.3, Q=2.5" if r["d"] == 2 else "N=1/6, Q=1/3",
+                    "params": "a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1", "seed": 0}),
         "roofline": {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, kd["name"]),
                      "kernel": kd["name"], "bytes_per_lu": kd["bytes_per_lu"],
-                     "algorithmic_bytes_per_launch": kd["bytes_per_lu"] * r["ns"]},
+                     "algorithmic_bytes_per_launch": kd["bytes_per_lu"] * kd.get("units", r["ns"])},
         "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
         "mlups_standard_stencil": r["mlups_standard"],
         "kernels": r["kernels"],

@@ -216,6 +216,95 @@ hlb_status hlb_destroy(hlb_ctx *ctx);
 /* Library version string. */
 const char *hlb_version(void);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent D2Q9 simulations.
+ *
+ * A batch advances nsim independent periodic D2Q9 simulations together, each
+ * with its own lattice size nx[b] x ny[b] and its own hlb_params (so its own
+ * tau, stencil weights N, Q, cd_Q, free-energy parameters, force form,
+ * body force and number of substeps m_b).  Every simulation computes exactly
+ * the timestep described at the top of this file (Sec. 2); the batch only
+ * shares launches: a step is one force + collide-and-stream launch over the
+ * tiles of all simulations, then max_b(m_b) substep launches, in which a
+ * simulation that has done its m_b substeps copies phi through.  The
+ * parameter sweeps of Sec. 3 (tau and the stencil pairs of Table I, the drop
+ * radii of the Laplace test) are the intended use: many small lattices that
+ * would each leave most of the device idle.
+ *
+ * Device storage: one caller-owned workspace of hlb_batch_workspace_size()
+ * bytes (256-byte aligned) holds every simulation's arrays plus the tile
+ * tables; nothing is allocated.  Steps are replayed from a HIP graph of two
+ * steps built on the first call (the graph objects are host-side).  The
+ * batch is not thread-safe.  Errors follow the conventions above;
+ * hlb_batch_last_error(NULL) reports failures of hlb_batch_create.
+ * ---------------------------------------------------------------------- */
+typedef struct hlb_batch hlb_batch;
+
+/* Bytes of device workspace for a batch of nsim simulations of sizes
+ * nx[b] x ny[b] (host arrays of nsim ints).  HLB_ESHAPE if a size is < 1 or
+ * nx*ny >= 2^31; HLB_EINVAL for nsim < 1 or NULL arguments. */
+hlb_status hlb_batch_workspace_size(int storage, int nsim, const int *nx, const int *ny, size_t *bytes);
+
+/* Creates a batch.  params: host array of nsim parameter sets, each checked
+ * as by hlb_check_params (fd_substeps 0 selects m_b automatically).  The
+ * workspace and stream follow the single-simulation conventions.  Copies the
+ * per-simulation descriptors and tile tables to the device and synchronises.
+ * Every simulation starts uninitialised: call hlb_batch_init_fields for each
+ * before stepping. */
+hlb_status hlb_batch_create(hlb_batch **out, int storage, int nsim, const int *nx, const int *ny,
+                            const hlb_params *params, void *workspace, size_t bytes, void *stream);
+
+/* Number of simulations, the largest m_b and (m_out, may be NULL, nsim ints)
+ * the substeps of every simulation. */
+hlb_status hlb_batch_info(const hlb_batch *b, int *nsim, int *max_m, int *m_out);
+
+/* Equilibrium initial state of simulation sim, as hlb_init_fields: phi
+ * (ns doubles), n (ns doubles, NULL = 1) and u (2*ns doubles, NULL = 0).
+ * Does not change the batch step counter.  Synchronises. */
+hlb_status hlb_batch_init_fields(hlb_batch *b, int sim, const double *phi, const double *n, const double *u);
+
+/* Advances every simulation of the batch by nsteps timesteps.  Enqueues
+ * work on the stream and returns without synchronising. */
+hlb_status hlb_batch_step(hlb_batch *b, long long nsteps);
+
+/* As hlb_batch_step, launched directly (no graph) with HIP events around
+ * the kernels of each step: ms[0] receives the total milliseconds of the
+ * collide-and-stream launches, ms[1] those of the substep launches.
+ * Synchronises. */
+hlb_status hlb_batch_step_timed(hlb_batch *b, long long nsteps, double ms[2]);
+
+/* Tile shapes of the batch's two launches: plan[0] indexes the
+ * collide-and-stream tiles {64x8, 32x8, 64x4, 32x16}, plan[1] the substep
+ * tiles {64x8, 32x8, 64x16, 32x16} (x by y sites).  HLB_EINVAL out of range.
+ * Rebuilds the tile tables and synchronises. */
+hlb_status hlb_batch_set_plan(hlb_batch *b, const int plan[2]);
+
+/* The current tile shapes: plan = {lb_x, lb_y, substep_x, substep_y}. */
+hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[4]);
+
+/* Times every candidate tile shape of both launches on the current state
+ * (the timed launches write only buffers that are not state between steps,
+ * so the state is unchanged), keeps the fastest of each and writes their
+ * times in microseconds per launch to us[0] (collide-and-stream) and us[1]
+ * (one substep over every simulation); us may be NULL.  Synchronises. */
+hlb_status hlb_batch_autotune(hlb_batch *b, double us[2]);
+
+/* Moments of simulation sim, as hlb_get_fields (2D: u has 2*ns values).
+ * Synchronises. */
+hlb_status hlb_batch_get_fields(hlb_batch *b, int sim, double *n, double *u, double *phi, double *mu);
+
+/* Global sums and maxima of simulation sim, as hlb_reduce (mom[2] = 0;
+ * step is the batch's step counter).  HLB_ENONFINITE if the simulation's
+ * state holds a non-finite value, HLB_EUNSTABLE if its max|u*| >= c_s/2.
+ * Synchronises. */
+hlb_status hlb_batch_reduce(hlb_batch *b, int sim, hlb_stats *out);
+
+/* Message of the batch's last failure; b may be NULL for hlb_batch_create. */
+const char *hlb_batch_last_error(const hlb_batch *b);
+
+/* Destroys the batch and its graphs.  Does not free the workspace. */
+hlb_status hlb_batch_destroy(hlb_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -6,4 +6,4 @@ The method runs in hand-written HIP kernels behind the C ABI of
 binding.
 """
 from . import hlb  # noqa: F401
-from .hlb import Sim, params, check_params, workspace_size, version  # noqa: F401
+from .hlb import Batch, Sim, params, check_params, workspace_size, batch_workspace_size, version  # noqa: F401

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -251,43 +252,45 @@ hlb_status hip_fail(hlb_ctx *c, hipError_t e, const char *what) {
   return fail(c, HLB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-KParams kparams(const hlb_ctx *c) {
+KParams make_kparams(int d, int nx, int ny, int nz, const hlb_params &p, int m) {
   KParams k{};
-  k.nx = c->nx;
-  k.ny = c->ny;
-  k.nz = c->nz;
-  k.ns = (int)c->ns;
-  k.a = c->p.a;
-  k.b = c->p.b;
-  k.kappa = c->p.kappa;
-  k.omega = 1.0 / c->p.tau;
-  k.gamma = c->p.gamma;
-  if (c->d == 2) {
-    k.gN = c->p.N;
-    k.gM = (1.0 - 2.0 * c->p.N) / 4.0;
-    k.lQ = c->p.Q;
-    k.lR = (1.0 - c->p.Q) / 2.0;
+  k.nx = nx;
+  k.ny = ny;
+  k.nz = nz;
+  k.ns = nx * ny * nz;
+  k.a = p.a;
+  k.b = p.b;
+  k.kappa = p.kappa;
+  k.omega = 1.0 / p.tau;
+  k.gamma = p.gamma;
+  if (d == 2) {
+    k.gN = p.N;
+    k.gM = (1.0 - 2.0 * p.N) / 4.0;
+    k.lQ = p.Q;
+    k.lR = (1.0 - p.Q) / 2.0;
     k.lC = -4.0 * (k.lQ + k.lR);
-    k.cQ = c->p.cd_Q;
-    k.cR = (1.0 - c->p.cd_Q) / 2.0;
+    k.cQ = p.cd_Q;
+    k.cR = (1.0 - p.cd_Q) / 2.0;
     k.cC = -4.0 * (k.cQ + k.cR);
   } else {
-    k.gN = c->p.N;
-    k.gM = (1.0 - 2.0 * c->p.N) / 8.0;
-    k.lQ = c->p.Q;
-    k.lR = (1.0 - c->p.Q) / 4.0;
+    k.gN = p.N;
+    k.gM = (1.0 - 2.0 * p.N) / 8.0;
+    k.lQ = p.Q;
+    k.lR = (1.0 - p.Q) / 4.0;
     k.lC = -(6.0 * k.lQ + 12.0 * k.lR);
-    k.cQ = c->p.cd_Q;
-    k.cR = (1.0 - c->p.cd_Q) / 4.0;
+    k.cQ = p.cd_Q;
+    k.cR = (1.0 - p.cd_Q) / 4.0;
     k.cC = -(6.0 * k.cQ + 12.0 * k.cR);
   }
-  k.dt = 1.0 / c->m;
-  for (int i = 0; i < 3; i++) k.g[i] = c->p.g_ext[i];
-  k.rho0 = c->p.rho0;
-  k.force_form = c->p.force_form;
-  k.advection = c->p.advection;
+  k.dt = 1.0 / m;
+  for (int i = 0; i < 3; i++) k.g[i] = p.g_ext[i];
+  k.rho0 = p.rho0;
+  k.force_form = p.force_form;
+  k.advection = p.advection;
   return k;
 }
+
+KParams kparams(const hlb_ctx *c) { return make_kparams(c->d, c->nx, c->ny, c->nz, c->p, c->m); }
 
 template <class T> T *at(hlb_ctx *c, size_t off) { return reinterpret_cast<T *>(c->ws + off); }
 
@@ -1027,5 +1030,674 @@ hlb_status hlb_destroy(hlb_ctx *c) {
 }
 
 const char *hlb_version(void) { return "hlb 0.1.0 (gfx950)"; }
+
+}  // extern "C"
+
+// ===================================================== batched simulations
+// A batch advances many independent periodic D2Q9 simulations of different
+// sizes and parameters together.  Every simulation has its own population,
+// phi and u* arrays in the caller's workspace and a descriptor (SimDesc) on
+// the device; tile tables map the blocks of one launch to (simulation, tile
+// origin).  A step is one force + collide-and-stream launch over the tiles of
+// all simulations, then, for s = 0 .. max_b(m_b) - 1, one substep launch over
+// the tiles of the simulations with m_b > s (the substep table lists the
+// simulations in decreasing m_b).  Steps are replayed from a HIP graph of two
+// steps.  The tile shapes of both launches are a plan chosen by
+// hlb_batch_autotune.
+
+namespace {
+
+struct TileShape {
+  int x, y;
+};
+// candidate tile shapes (256 threads per block)
+constexpr TileShape kBatchLB[] = {{64, 8}, {32, 8}, {64, 4}, {32, 16}};
+constexpr TileShape kBatchCH[] = {{64, 8}, {32, 8}, {64, 16}, {32, 16}};
+constexpr int kNumLB = sizeof(kBatchLB) / sizeof(kBatchLB[0]);
+constexpr int kNumCH = sizeof(kBatchCH) / sizeof(kBatchCH[0]);
+
+}  // namespace
+
+struct hlb_batch {
+  int storage, nsim;
+  std::vector<int> nx, ny, m;
+  std::vector<hlb_params> p;
+  std::vector<int> order;  // simulations in decreasing m (stable)
+  bool lap5;               // every simulation has cd_Q = 1
+  hipStream_t stream;
+  char *ws;
+  size_t desc_off, lbt_off, cht_off, g_off, phi_off, u_off, io_off, part_off, out_off, total;
+  std::vector<long long> g_el, phi_el, u_el;  // per-simulation element offsets of buffer 0
+  int max_m;
+  int lb_plan, ch_plan;       // indices into the candidate tile shapes
+  int nlb;                    // blocks of the collide-and-stream launch
+  std::vector<int> nch;       // blocks of substep launch s
+  int par;                    // step parity
+  long long step;
+  hipGraphExec_t exec[2];
+  bool have_exec[2];
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+hlb_status bfail(hlb_batch *b, hlb_status s, const std::string &msg) {
+  if (b) b->err = msg;
+  else g_batch_error = msg;
+  return s;
+}
+
+struct BatchLayout {
+  size_t desc, lbt, cht, g, phi, u, io, part, out, total;
+  std::vector<long long> g_el, phi_el, u_el;
+};
+
+int count_tiles(int nsim, const int *nx, const int *ny, TileShape t) {
+  long long c = 0;
+  for (int i = 0; i < nsim; i++) c += (long long)ceil_div(nx[i], t.x) * ceil_div(ny[i], t.y);
+  return c > (1LL << 30) ? -1 : (int)c;
+}
+
+BatchLayout batch_layout(int storage, int nsim, const int *nx, const int *ny) {
+  BatchLayout L{};
+  const size_t es = storage == HLB_F64 ? 8 : 4;
+  long long gel = 0, pel = 0, uel = 0, max_ns = 0;
+  int max_part = 0, max_lb = 0, max_ch = 0;
+  const int rtx = storage == HLB_F64 ? Tiles<D2Q9, double>::LB[0] : Tiles<D2Q9, float>::LB[0];
+  const int rty = storage == HLB_F64 ? Tiles<D2Q9, double>::LB[1] : Tiles<D2Q9, float>::LB[1];
+  for (int i = 0; i < nsim; i++) {
+    const long long ns = (long long)nx[i] * ny[i];
+    L.g_el.push_back(gel);
+    L.phi_el.push_back(pel);
+    L.u_el.push_back(uel);
+    // each array rounded up to 64 elements: every array starts 256-byte aligned
+    gel += 2 * (((9 * ns) + 63) / 64) * 64;
+    pel += 2 * ((ns + 63) / 64) * 64;
+    uel += ((2 * ns + 63) / 64) * 64;
+    max_ns = std::max(max_ns, ns);
+    max_part = std::max(max_part, ceil_div(nx[i], rtx) * ceil_div(ny[i], rty));
+  }
+  for (auto t : kBatchLB) max_lb = std::max(max_lb, count_tiles(nsim, nx, ny, t));
+  for (auto t : kBatchCH) max_ch = std::max(max_ch, count_tiles(nsim, nx, ny, t));
+  size_t off = 0;
+  L.desc = off;
+  off = align_up(off + sizeof(SimDesc) * nsim);
+  L.lbt = off;
+  off = align_up(off + sizeof(TileRef) * max_lb);
+  L.cht = off;
+  off = align_up(off + sizeof(TileRef) * max_ch);
+  L.g = off;
+  off = align_up(off + es * gel);
+  L.phi = off;
+  off = align_up(off + es * pel);
+  L.u = off;
+  off = align_up(off + es * uel);
+  L.io = off;
+  off = align_up(off + 5 * 8 * (size_t)max_ns);
+  L.part = off;
+  off = align_up(off + (size_t)max_part * 8 * 8);
+  L.out = off;
+  off = align_up(off + 8 * 8);
+  L.total = off;
+  return L;
+}
+
+hlb_status batch_shapes(int nsim, const int *nx, const int *ny, std::string *msg) {
+  if (nsim < 1 || !nx || !ny) {
+    *msg = "nsim must be >= 1 and nx, ny non-NULL";
+    return HLB_EINVAL;
+  }
+  for (int i = 0; i < nsim; i++)
+    if (nx[i] < 1 || ny[i] < 1 || (long long)nx[i] * ny[i] >= (1LL << 31)) {
+      *msg = "every simulation needs nx, ny >= 1 and nx*ny < 2^31";
+      return HLB_ESHAPE;
+    }
+  for (auto t : kBatchLB)
+    if (count_tiles(nsim, nx, ny, t) < 0) {
+      *msg = "too many tiles in the batch (more than 2^30)";
+      return HLB_ESHAPE;
+    }
+  return HLB_OK;
+}
+
+template <typename T>
+T *bat(hlb_batch *b, size_t off) {
+  return reinterpret_cast<T *>(b->ws + off);
+}
+
+// Tile tables of the current plan, copied to the device; blocks per launch.
+hlb_status batch_tables(hlb_batch *b) {
+  const TileShape tl = kBatchLB[b->lb_plan], tc = kBatchCH[b->ch_plan];
+  std::vector<TileRef> lbt, cht;
+  for (int i = 0; i < b->nsim; i++)
+    for (int y = 0; y < b->ny[i]; y += tl.y)
+      for (int x = 0; x < b->nx[i]; x += tl.x) lbt.push_back(TileRef{i, x, y, 0});
+  b->nch.assign(b->max_m, 0);
+  for (int i : b->order) {
+    for (int y = 0; y < b->ny[i]; y += tc.y)
+      for (int x = 0; x < b->nx[i]; x += tc.x) cht.push_back(TileRef{i, x, y, 0});
+    for (int s = 0; s < b->m[i]; s++) b->nch[s] = (int)cht.size();
+  }
+  b->nlb = (int)lbt.size();
+  hipError_t e = hipMemcpyAsync(b->ws + b->lbt_off, lbt.data(), sizeof(TileRef) * lbt.size(), hipMemcpyHostToDevice,
+                                b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->cht_off, cht.data(), sizeof(TileRef) * cht.size(), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("batch tile tables: ") + hipGetErrorString(e));
+  for (int i = 0; i < 2; i++)
+    if (b->have_exec[i]) {
+      (void)hipGraphExecDestroy(b->exec[i]);
+      b->have_exec[i] = false;
+    }
+  return HLB_OK;
+}
+
+// Kernel entry of the collide-and-stream launch and of the substep launch for
+// the plan; arguments follow k_lb_batch and k_ch_batch.
+template <typename T, int I>
+const void *lb_fn_i(int i) {
+  if constexpr (I == kNumLB) {
+    return nullptr;
+  } else {
+    if (i == I) return reinterpret_cast<const void *>(&k_lb_batch<T, kBatchLB[I].x, kBatchLB[I].y>);
+    return lb_fn_i<T, I + 1>(i);
+  }
+}
+
+template <typename T, int I>
+const void *ch_fn_i(int i, bool lap5) {
+  if constexpr (I == kNumCH) {
+    return nullptr;
+  } else {
+    if (i == I)
+      return lap5 ? reinterpret_cast<const void *>(&k_ch_batch<T, kBatchCH[I].x, kBatchCH[I].y, true>)
+                  : reinterpret_cast<const void *>(&k_ch_batch<T, kBatchCH[I].x, kBatchCH[I].y, false>);
+    return ch_fn_i<T, I + 1>(i, lap5);
+  }
+}
+
+const void *lb_fn(const hlb_batch *b, int plan) {
+  return b->storage == HLB_F64 ? lb_fn_i<double, 0>(plan) : lb_fn_i<float, 0>(plan);
+}
+const void *ch_fn(const hlb_batch *b, int plan) {
+  return b->storage == HLB_F64 ? ch_fn_i<double, 0>(plan, b->lap5) : ch_fn_i<float, 0>(plan, b->lap5);
+}
+
+// Launch arguments of the two batch kernels (the pointers are typed by the
+// storage; every pointer has the same size, so void* stands in for them).
+struct LbArgs {
+  const void *sims, *tiles;
+  void *g, *phi, *u;
+  int par;
+  void *slot[6];
+  void **bind() {
+    slot[0] = &sims;
+    slot[1] = &tiles;
+    slot[2] = &g;
+    slot[3] = &phi;
+    slot[4] = &u;
+    slot[5] = &par;
+    return slot;
+  }
+};
+struct ChArgs {
+  const void *sims, *tiles;
+  void *phi;
+  const void *u;
+  int par, s;
+  void *slot[6];
+  void **bind() {
+    slot[0] = &sims;
+    slot[1] = &tiles;
+    slot[2] = &phi;
+    slot[3] = &u;
+    slot[4] = &par;
+    slot[5] = &s;
+    return slot;
+  }
+};
+
+LbArgs lb_args(hlb_batch *b, int par) {
+  return LbArgs{b->ws + b->desc_off, b->ws + b->lbt_off, b->ws + b->g_off, b->ws + b->phi_off, b->ws + b->u_off, par, {}};
+}
+ChArgs ch_args(hlb_batch *b, int par, int s) {
+  return ChArgs{b->ws + b->desc_off, b->ws + b->cht_off, b->ws + b->phi_off, b->ws + b->u_off, par, s, {}};
+}
+
+hipError_t launch_lb(hlb_batch *b, int plan, int par) {
+  LbArgs a = lb_args(b, par);
+  return hipLaunchKernel(lb_fn(b, plan), dim3(b->nlb), dim3(NT), a.bind(), 0, b->stream);
+}
+hipError_t launch_ch(hlb_batch *b, int plan, int par, int s, int nblk) {
+  ChArgs a = ch_args(b, par, s);
+  return hipLaunchKernel(ch_fn(b, plan), dim3(nblk), dim3(NT), a.bind(), 0, b->stream);
+}
+
+hipError_t batch_enqueue_step(hlb_batch *b, int par) {
+  hipError_t e = launch_lb(b, b->lb_plan, par);
+  for (int s = 0; s < b->max_m && e == hipSuccess; s++) e = launch_ch(b, b->ch_plan, par, s, b->nch[s]);
+  return e;
+}
+
+// A graph of two steps from parity par, built from kernel nodes (no stream
+// capture, so the caller's stream may be the legacy default stream).
+hlb_status batch_build_graph(hlb_batch *b, int par, hipGraphExec_t *exec) {
+  hipGraph_t graph;
+  hipError_t e = hipGraphCreate(&graph, 0);
+  if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("hipGraphCreate: ") + hipGetErrorString(e));
+  hipGraphNode_t prev = nullptr;
+  for (int st = 0; st < 2 && e == hipSuccess; st++) {
+    const int pp = (par + st) & 1;
+    LbArgs la = lb_args(b, pp);
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(lb_fn(b, b->lb_plan));
+    kp.gridDim = dim3(b->nlb);
+    kp.blockDim = dim3(NT);
+    kp.kernelParams = la.bind();
+    hipGraphNode_t node;
+    e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e == hipSuccess) prev = node;
+    for (int s = 0; s < b->max_m && e == hipSuccess; s++) {
+      ChArgs ca = ch_args(b, pp, s);
+      hipKernelNodeParams kc{};
+      kc.func = const_cast<void *>(ch_fn(b, b->ch_plan));
+      kc.gridDim = dim3(b->nch[s]);
+      kc.blockDim = dim3(NT);
+      kc.kernelParams = ca.bind();
+      e = hipGraphAddKernelNode(&node, graph, &prev, 1, &kc);
+      if (e == hipSuccess) prev = node;
+    }
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("batch graph: ") + hipGetErrorString(e));
+  return HLB_OK;
+}
+
+hlb_status bsync(hlb_batch *b) {
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+  return HLB_OK;
+}
+
+hlb_status bcheck(hlb_batch *b, hipError_t e, const char *what) {
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  return HLB_OK;
+}
+
+KParams sim_kparams(const hlb_batch *b, int i) { return make_kparams(2, b->nx[i], b->ny[i], 1, b->p[i], b->m[i]); }
+
+// Device pointers of simulation i's current populations and phi.
+template <typename T>
+void sim_state(hlb_batch *b, int i, T **g, T **phi) {
+  const size_t ns = (size_t)b->nx[i] * b->ny[i];
+  const size_t gstride = ((9 * ns + 63) / 64) * 64, pstride = ((ns + 63) / 64) * 64;
+  *g = bat<T>(b, b->g_off) + b->g_el[i] + (b->par ? gstride : 0);
+  *phi = bat<T>(b, b->phi_off) + b->phi_el[i] + ((b->par & b->m[i] & 1) ? pstride : 0);
+}
+
+template <typename T>
+void sim_readout(hlb_batch *b, int i) {
+  using TL = Tiles<D2Q9, T>;
+  T *g, *phi;
+  sim_state<T>(b, i, &g, &phi);
+  const dim3 grid(ceil_div(b->nx[i], TL::LB[0]), ceil_div(b->ny[i], TL::LB[1]));
+  hipLaunchKernelGGL((k_readout<D2Q9, T, TL::LB[0], TL::LB[1], 1>), grid, dim3(256), 0, b->stream,
+                     sim_kparams(b, i), g, phi, bat<double>(b, b->io_off));
+}
+
+template <typename T>
+int sim_reduce(hlb_batch *b, int i) {
+  using TL = Tiles<D2Q9, T>;
+  T *g, *phi;
+  sim_state<T>(b, i, &g, &phi);
+  const dim3 grid(ceil_div(b->nx[i], TL::LB[0]), ceil_div(b->ny[i], TL::LB[1]));
+  hipLaunchKernelGGL((k_reduce<D2Q9, T, TL::LB[0], TL::LB[1], 1>), grid, dim3(256), 0, b->stream, sim_kparams(b, i),
+                     g, phi, bat<double>(b, b->part_off));
+  return grid.x * grid.y;
+}
+
+template <typename T>
+void sim_init(hlb_batch *b, int i) {
+  T *g, *phi;
+  sim_state<T>(b, i, &g, &phi);
+  const size_t ns = (size_t)b->nx[i] * b->ny[i];
+  hipLaunchKernelGGL((k_init<D2Q9, T>), dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, b->stream,
+                     sim_kparams(b, i), bat<double>(b, b->io_off), g, phi);
+}
+
+}  // namespace
+
+extern "C" {
+
+hlb_status hlb_batch_workspace_size(int storage, int nsim, const int *nx, const int *ny, size_t *bytes) {
+  std::string msg;
+  if (!bytes || (storage != HLB_F64 && storage != HLB_F32_SHIFTED))
+    return bfail(nullptr, HLB_EINVAL, "bytes is NULL or the storage is unknown");
+  hlb_status s = batch_shapes(nsim, nx, ny, &msg);
+  if (s != HLB_OK) return bfail(nullptr, s, msg);
+  *bytes = batch_layout(storage, nsim, nx, ny).total;
+  return HLB_OK;
+}
+
+hlb_status hlb_batch_create(hlb_batch **out, int storage, int nsim, const int *nx, const int *ny,
+                            const hlb_params *params, void *workspace, size_t bytes, void *stream) {
+  std::string msg;
+  if (!out) return bfail(nullptr, HLB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (storage != HLB_F64 && storage != HLB_F32_SHIFTED) return bfail(nullptr, HLB_EINVAL, "unknown storage");
+  hlb_status s = batch_shapes(nsim, nx, ny, &msg);
+  if (s != HLB_OK) return bfail(nullptr, s, msg);
+  if (!params) return bfail(nullptr, HLB_EINVAL, "params is NULL");
+  std::vector<int> ms(nsim);
+  for (int i = 0; i < nsim; i++) {
+    s = validate(HLB_D2Q9, &params[i], &ms[i], &msg);
+    if (s != HLB_OK) return bfail(nullptr, s, "simulation " + std::to_string(i) + ": " + msg);
+  }
+  const BatchLayout L = batch_layout(storage, nsim, nx, ny);
+  if (!workspace || bytes < L.total) return bfail(nullptr, HLB_ESHAPE, "workspace missing or too small");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+    return bfail(nullptr, HLB_EINVAL, "workspace must be 256-byte aligned");
+  hlb_batch *b = new (std::nothrow) hlb_batch();
+  if (!b) return bfail(nullptr, HLB_EINVAL, "out of host memory");
+  b->storage = storage;
+  b->nsim = nsim;
+  b->nx.assign(nx, nx + nsim);
+  b->ny.assign(ny, ny + nsim);
+  b->m = ms;
+  b->p.assign(params, params + nsim);
+  b->order.resize(nsim);
+  for (int i = 0; i < nsim; i++) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return ms[x] > ms[y]; });
+  b->lap5 = true;
+  for (int i = 0; i < nsim; i++) b->lap5 = b->lap5 && params[i].cd_Q == 1.0;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->ws = reinterpret_cast<char *>(workspace);
+  b->desc_off = L.desc;
+  b->lbt_off = L.lbt;
+  b->cht_off = L.cht;
+  b->g_off = L.g;
+  b->phi_off = L.phi;
+  b->u_off = L.u;
+  b->io_off = L.io;
+  b->part_off = L.part;
+  b->out_off = L.out;
+  b->total = L.total;
+  b->g_el = L.g_el;
+  b->phi_el = L.phi_el;
+  b->u_el = L.u_el;
+  b->max_m = *std::max_element(ms.begin(), ms.end());
+  b->lb_plan = 0;
+  b->ch_plan = 0;
+  b->par = 0;
+  b->step = 0;
+  b->have_exec[0] = b->have_exec[1] = false;
+  std::vector<SimDesc> desc(nsim);
+  for (int i = 0; i < nsim; i++) {
+    const long long ns = (long long)nx[i] * ny[i];
+    desc[i].p = make_kparams(2, nx[i], ny[i], 1, params[i], ms[i]);
+    desc[i].g[0] = L.g_el[i];
+    desc[i].g[1] = L.g_el[i] + ((9 * ns + 63) / 64) * 64;
+    desc[i].phi[0] = L.phi_el[i];
+    desc[i].phi[1] = L.phi_el[i] + ((ns + 63) / 64) * 64;
+    desc[i].u = L.u_el[i];
+    desc[i].m = ms[i];
+    desc[i].pad = 0;
+  }
+  hipError_t e = hipMemcpyAsync(b->ws + L.desc, desc.data(), sizeof(SimDesc) * nsim, hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) {
+    delete b;
+    return bfail(nullptr, HLB_EHIP, std::string("batch descriptors: ") + hipGetErrorString(e));
+  }
+  s = batch_tables(b);
+  if (s != HLB_OK) {
+    g_batch_error = b->err;
+    delete b;
+    return s;
+  }
+  *out = b;
+  return HLB_OK;
+}
+
+hlb_status hlb_batch_info(const hlb_batch *b, int *nsim, int *max_m, int *m_out) {
+  if (!b) return HLB_EINVAL;
+  if (nsim) *nsim = b->nsim;
+  if (max_m) *max_m = b->max_m;
+  if (m_out)
+    for (int i = 0; i < b->nsim; i++) m_out[i] = b->m[i];
+  return HLB_OK;
+}
+
+hlb_status hlb_batch_init_fields(hlb_batch *b, int sim, const double *phi, const double *n, const double *u) {
+  if (!b) return HLB_EINVAL;
+  if (sim < 0 || sim >= b->nsim || !phi) return bfail(b, HLB_EINVAL, "bad simulation index or phi is NULL");
+  const size_t ns = (size_t)b->nx[sim] * b->ny[sim];
+  std::vector<double> host(4 * ns);
+  std::memcpy(host.data(), phi, ns * 8);
+  if (n) std::memcpy(host.data() + ns, n, ns * 8);
+  else std::fill(host.begin() + ns, host.begin() + 2 * ns, 1.0);
+  if (u) std::memcpy(host.data() + 2 * ns, u, 2 * ns * 8);
+  else std::fill(host.begin() + 2 * ns, host.end(), 0.0);
+  if (!finite_all(host.data(), host.size())) return bfail(b, HLB_ENONFINITE, "non-finite value in the initial fields");
+  for (size_t i = 0; i < ns; i++)
+    if (!(host[ns + i] > 0)) return bfail(b, HLB_ENONFINITE, "initial density must be > 0");
+  hipError_t e = hipMemcpyAsync(b->ws + b->io_off, host.data(), host.size() * 8, hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+  if (b->storage == HLB_F64) sim_init<double>(b, sim);
+  else sim_init<float>(b, sim);
+  hlb_status s = bcheck(b, hipSuccess, "init kernel");
+  if (s != HLB_OK) return s;
+  return bsync(b);
+}
+
+hlb_status hlb_batch_step(hlb_batch *b, long long nsteps) {
+  if (!b) return HLB_EINVAL;
+  if (nsteps < 0) return bfail(b, HLB_EINVAL, "nsteps must be >= 0");
+  long long left = nsteps;
+  while (left >= 2) {
+    if (!b->have_exec[b->par]) {
+      hlb_status s = batch_build_graph(b, b->par, &b->exec[b->par]);
+      if (s != HLB_OK) return s;
+      b->have_exec[b->par] = true;
+    }
+    hipError_t e = hipGraphLaunch(b->exec[b->par], b->stream);
+    if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+    b->step += 2;  // parity unchanged
+    left -= 2;
+  }
+  if (left == 1) {
+    hlb_status s = bcheck(b, batch_enqueue_step(b, b->par), "batch step");
+    if (s != HLB_OK) return s;
+    b->par ^= 1;
+    b->step += 1;
+  }
+  return HLB_OK;
+}
+
+hlb_status hlb_batch_step_timed(hlb_batch *b, long long nsteps, double ms[2]) {
+  if (!b) return HLB_EINVAL;
+  if (nsteps < 0 || !ms) return bfail(b, HLB_EINVAL, "nsteps must be >= 0 and ms non-NULL");
+  ms[0] = ms[1] = 0.0;
+  constexpr int kChunk = 64;
+  std::vector<hipEvent_t> ev(3 * kChunk);
+  for (auto &e : ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return bfail(b, HLB_EHIP, std::string("hipEventCreate: ") + hipGetErrorString(r));
+  }
+  long long done = 0;
+  hlb_status st = HLB_OK;
+  while (done < nsteps && st == HLB_OK) {
+    const int n = (int)std::min<long long>(kChunk, nsteps - done);
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < n && e == hipSuccess; t++) {
+      e = hipEventRecord(ev[3 * t], b->stream);
+      if (e == hipSuccess) e = launch_lb(b, b->lb_plan, b->par);
+      if (e == hipSuccess) e = hipEventRecord(ev[3 * t + 1], b->stream);
+      for (int s = 0; s < b->max_m && e == hipSuccess; s++) e = launch_ch(b, b->ch_plan, b->par, s, b->nch[s]);
+      if (e == hipSuccess) e = hipEventRecord(ev[3 * t + 2], b->stream);
+      if (e == hipSuccess) {
+        b->par ^= 1;
+        b->step += 1;
+      }
+    }
+    st = bcheck(b, e, "batch step kernels");
+    if (st != HLB_OK) break;
+    st = bsync(b);
+    if (st != HLB_OK) break;
+    for (int t = 0; t < n; t++) {
+      float x = 0, y = 0;
+      (void)hipEventElapsedTime(&x, ev[3 * t], ev[3 * t + 1]);
+      (void)hipEventElapsedTime(&y, ev[3 * t + 1], ev[3 * t + 2]);
+      ms[0] += x;
+      ms[1] += y;
+    }
+    done += n;
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  return st;
+}
+
+hlb_status hlb_batch_set_plan(hlb_batch *b, const int plan[2]) {
+  if (!b || !plan) return HLB_EINVAL;
+  if (plan[0] < 0 || plan[0] >= kNumLB || plan[1] < 0 || plan[1] >= kNumCH)
+    return bfail(b, HLB_EINVAL, "plan indices out of range");
+  b->lb_plan = plan[0];
+  b->ch_plan = plan[1];
+  return batch_tables(b);
+}
+
+hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[4]) {
+  if (!b || !plan) return HLB_EINVAL;
+  plan[0] = kBatchLB[b->lb_plan].x;
+  plan[1] = kBatchLB[b->lb_plan].y;
+  plan[2] = kBatchCH[b->ch_plan].x;
+  plan[3] = kBatchCH[b->ch_plan].y;
+  return HLB_OK;
+}
+
+hlb_status hlb_batch_autotune(hlb_batch *b, double us[2]) {
+  if (!b) return HLB_EINVAL;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return bfail(b, HLB_EHIP, "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return bfail(b, HLB_EHIP, "hipEventCreate");
+  }
+  constexpr int REPS = 5;
+  double best[2] = {1e300, 1e300};
+  int pick[2] = {b->lb_plan, b->ch_plan};
+  hlb_status st = HLB_OK;
+  // The collide-and-stream kernel reads populations[par] and phi and writes
+  // the other population buffer and u*, neither of which is state between
+  // steps; substep 0 reads phi and u* and writes the spare phi buffer.  So
+  // timing either leaves the state as it was.  Each class is timed with the
+  // best shape of the classes before it.
+  for (int cls = 0; cls < 2 && st == HLB_OK; cls++) {
+    const int ncand = cls == 0 ? kNumLB : kNumCH;
+    for (int c = 0; c < ncand && st == HLB_OK; c++) {
+      if (cls == 0) b->lb_plan = c;
+      else b->ch_plan = c;
+      st = batch_tables(b);
+      if (st != HLB_OK) break;
+      // the first launch (untimed) gives u* its values for the substeps
+      hipError_t e = launch_lb(b, b->lb_plan, b->par);
+      for (int r = 0; r < 1 + REPS && e == hipSuccess; r++) {
+        if (r == 1) e = hipEventRecord(e0, b->stream);
+        if (e != hipSuccess) break;
+        e = cls == 0 ? launch_lb(b, b->lb_plan, b->par) : launch_ch(b, b->ch_plan, b->par, 0, b->nch[0]);
+      }
+      if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = bfail(b, HLB_EHIP, std::string("batch autotune: ") + hipGetErrorString(e));
+        break;
+      }
+      const double t = 1e3 * ms / REPS;
+      if (t < best[cls]) {
+        best[cls] = t;
+        pick[cls] = c;
+      }
+    }
+    if (cls == 0) b->lb_plan = pick[0];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != HLB_OK) return st;
+  b->lb_plan = pick[0];
+  b->ch_plan = pick[1];
+  st = batch_tables(b);
+  if (st != HLB_OK) return st;
+  if (us) {
+    us[0] = best[0];
+    us[1] = best[1];
+  }
+  return HLB_OK;
+}
+
+hlb_status hlb_batch_get_fields(hlb_batch *b, int sim, double *n, double *u, double *phi, double *mu) {
+  if (!b) return HLB_EINVAL;
+  if (sim < 0 || sim >= b->nsim) return bfail(b, HLB_EINVAL, "bad simulation index");
+  const size_t ns = (size_t)b->nx[sim] * b->ny[sim];
+  if (b->storage == HLB_F64) sim_readout<double>(b, sim);
+  else sim_readout<float>(b, sim);
+  hlb_status s = bcheck(b, hipSuccess, "readout kernel");
+  if (s != HLB_OK) return s;
+  const double *io = bat<double>(b, b->io_off);
+  struct Part {
+    double *dst;
+    size_t off, count;
+  } parts[4] = {{n, 0, ns}, {u, ns, 2 * ns}, {phi, 3 * ns, ns}, {mu, 4 * ns, ns}};
+  for (auto &pt : parts) {
+    if (!pt.dst) continue;
+    hipError_t e = hipMemcpyAsync(pt.dst, io + pt.off, pt.count * 8, hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+  }
+  return bsync(b);
+}
+
+hlb_status hlb_batch_reduce(hlb_batch *b, int sim, hlb_stats *out) {
+  if (!b || !out) return HLB_EINVAL;
+  if (sim < 0 || sim >= b->nsim) return bfail(b, HLB_EINVAL, "bad simulation index");
+  const int nblk = b->storage == HLB_F64 ? sim_reduce<double>(b, sim) : sim_reduce<float>(b, sim);
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, b->stream, nblk, bat<double>(b, b->part_off),
+                     bat<double>(b, b->out_off));
+  hlb_status s = bcheck(b, hipSuccess, "reduce kernels");
+  if (s != HLB_OK) return s;
+  double r[8];
+  hipError_t e = hipMemcpyAsync(r, b->ws + b->out_off, sizeof r, hipMemcpyDeviceToHost, b->stream);
+  if (e != hipSuccess) return bfail(b, HLB_EHIP, std::string("hipMemcpyAsync: ") + hipGetErrorString(e));
+  s = bsync(b);
+  if (s != HLB_OK) return s;
+  std::memset(out, 0, sizeof *out);
+  out->mass = r[0];
+  out->phi_sum = r[1];
+  out->kinetic = r[2];
+  out->mom[0] = r[3];
+  out->mom[1] = r[4];
+  out->umax = r[6];
+  out->step = b->step;
+  out->finite = r[7] == 0.0 ? 1 : 0;
+  if (!out->finite) return bfail(b, HLB_ENONFINITE, "the state holds a non-finite value");
+  if (out->umax >= 0.5 * std::sqrt(1.0 / 3.0))
+    return bfail(b, HLB_EUNSTABLE, "max|u*| >= c_s/2: outside the low-Mach regime of the scheme");
+  return HLB_OK;
+}
+
+const char *hlb_batch_last_error(const hlb_batch *b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+hlb_status hlb_batch_destroy(hlb_batch *b) {
+  if (!b) return HLB_OK;
+  for (int i = 0; i < 2; i++)
+    if (b->have_exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+  delete b;
+  return HLB_OK;
+}
 
 }  // extern "C"

@@ -353,15 +353,12 @@ __device__ __forceinline__ void collide(const T f[L::Q], T dn, T n, const T u[3]
 // (Eqs. espdistrfunc, forceevoleqn, latticeforceterm) + streaming.
 // Writes the post-collision populations of time t at r (pull storage) and u*_t.
 template <class L, typename T, int TX, int TY, int TZ>
-__global__ void __launch_bounds__(NT) k_lb(KParams p, const T *__restrict__ gin, T *__restrict__ gout,
-                                           const T *__restrict__ phi, T *__restrict__ uout) {
+__device__ __forceinline__ void lb_tile(const KParams &p, const T *__restrict__ gin, T *__restrict__ gout,
+                                        const T *__restrict__ phi, T *__restrict__ uout, int x0, int y0, int z0) {
   constexpr int D = L::D;
   constexpr int NSITE = (TX * TY * TZ + NT - 1) / NT;  // sites per thread
   using FT = ForceTile<D, T, TX, TY, TZ>;
   __shared__ FT tile;
-  int bx, by, bz;
-  tile_coords(bx, by, bz);
-  const int x0 = bx * TX, y0 = by * TY, z0 = D == 3 ? bz * TZ : 0;
 
   // all global loads first: this thread's populations, then the phi tile
   T f[NSITE][L::Q];
@@ -408,6 +405,14 @@ __global__ void __launch_bounds__(NT) k_lb(KParams p, const T *__restrict__ gin,
   }
 }
 
+template <class L, typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(NT) k_lb(KParams p, const T *__restrict__ gin, T *__restrict__ gout,
+                                           const T *__restrict__ phi, T *__restrict__ uout) {
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  lb_tile<L, T, TX, TY, TZ>(p, gin, gout, phi, uout, bx * TX, by * TY, L::D == 3 ? bz * TZ : 0);
+}
+
 // One convection-diffusion substep (Sec. 2.3): advection half-step
 // h = phi - dt [phi div_c u + u . D^up phi] (Eqs. adv, centrdiff, backdiff,
 // fordiff; or the flux form), then phi' = h + dt Gamma L[a h + b phi^3 - kappa L h],
@@ -416,8 +421,8 @@ __global__ void __launch_bounds__(NT) k_lb(KParams p, const T *__restrict__ gin,
 // tile plus a halo of 2 and the diffusion potential on the tile plus 1, all
 // in LDS.  LAP5: the Laplacian has no edge weights (cd_Q = 1).
 template <class L, typename T, int TX, int TY, int TZ, bool LAP5>
-__global__ void __launch_bounds__(NT) k_ch(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
-                                            T *__restrict__ phi_out) {
+__device__ __forceinline__ void ch_tile(const KParams &p, const T *__restrict__ phi_in, const T *__restrict__ u,
+                                        T *__restrict__ phi_out, int x0, int y0, int z0) {
   constexpr int D = L::D;
   constexpr int H = 3;
   constexpr int PX = TX + 6, PY = TY + 6, PZ = D == 3 ? TZ + 6 : 1;
@@ -427,9 +432,6 @@ __global__ void __launch_bounds__(NT) k_ch(KParams p, const T *__restrict__ phi_
   __shared__ T su[D][PZ][PY][PX];
   __shared__ T sh[HZ][HY][HX];
   __shared__ T smu[MZ][MY][MX];
-  int bx, by, bz;
-  tile_coords(bx, by, bz);
-  const int x0 = bx * TX, y0 = by * TY, z0 = D == 3 ? bz * TZ : 0;
   const int nx = p.nx, ny = p.ny, nz = p.nz;
   const size_t ns = (size_t)p.ns;
   {
@@ -495,6 +497,62 @@ __global__ void __launch_bounds__(NT) k_ch(KParams p, const T *__restrict__ phi_
     const T Lmu = LAP5 ? lap5_at<D>(smu, mx, my, mz, cQ, cC) : lap_at<D>(smu, mx, my, mz, cQ, cR, cC);
     phi_out[x + nx * (y + ny * z)] = sh[hz][hy][hx] + dtg * Lmu;
   }
+}
+
+template <class L, typename T, int TX, int TY, int TZ, bool LAP5>
+__global__ void __launch_bounds__(NT) k_ch(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
+                                            T *__restrict__ phi_out) {
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  ch_tile<L, T, TX, TY, TZ, LAP5>(p, phi_in, u, phi_out, bx * TX, by * TY, L::D == 3 ? bz * TZ : 0);
+}
+
+// ------------------------------------------------------- batched simulations
+// Many independent periodic D2Q9 simulations of different sizes and
+// parameters advanced together: one launch covers the tiles of every
+// simulation, each block looking up its tile and its simulation.
+struct SimDesc {
+  KParams p;            // lattice size, coefficients and dt = 1/m of this simulation
+  long long g[2];       // element offsets of the two population buffers
+  long long phi[2];     // element offsets of the two phi buffers
+  long long u;          // element offset of u*
+  int m;                // convection-diffusion substeps per step
+  int pad;
+};
+
+struct TileRef {
+  int sim, x0, y0, pad;
+};
+
+// Batched simulations share one step parity `par` (steps since the start,
+// mod 2): populations are read from buffer par and written to 1 - par; a
+// simulation's phi starts step t in buffer (t m) mod 2 = par & m & 1, since
+// each of its m substeps flips it.
+__device__ __forceinline__ int batch_phi_buf(int par, int m) { return par & m & 1; }
+
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(NT) k_lb_batch(const SimDesc *__restrict__ sims, const TileRef *__restrict__ tiles,
+                                                 T *__restrict__ g, T *__restrict__ phi, T *__restrict__ u, int par) {
+  int b, unused1, unused2;
+  tile_coords(b, unused1, unused2);
+  const TileRef tr = tiles[b];
+  const SimDesc sd = sims[tr.sim];
+  lb_tile<D2Q9, T, TX, TY, 1>(sd.p, g + sd.g[par], g + sd.g[1 - par], phi + sd.phi[batch_phi_buf(par, sd.m)],
+                              u + sd.u, tr.x0, tr.y0, 0);
+}
+
+// Substep s of every simulation with m > s.  The substep tile table lists
+// the simulations in decreasing m, so the launch of substep s covers a
+// prefix of it and every block has work.
+template <typename T, int TX, int TY, bool LAP5>
+__global__ void __launch_bounds__(NT) k_ch_batch(const SimDesc *__restrict__ sims, const TileRef *__restrict__ tiles,
+                                                 T *__restrict__ phi, const T *__restrict__ u, int par, int s) {
+  int b, unused1, unused2;
+  tile_coords(b, unused1, unused2);
+  const TileRef tr = tiles[b];
+  const SimDesc sd = sims[tr.sim];
+  const int src = (batch_phi_buf(par, sd.m) + s) & 1;
+  ch_tile<D2Q9, T, TX, TY, 1, LAP5>(sd.p, phi + sd.phi[src], u + sd.u, phi + sd.phi[1 - src], tr.x0, tr.y0, 0);
 }
 
 // M convection-diffusion substeps in one pass (2D, standard 5-point

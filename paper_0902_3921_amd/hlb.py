@@ -27,7 +27,11 @@ STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ESHAPE", -3: "HLB_EUNSTA
 EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_create",
            "hlb_set_params", "hlb_get_params", "hlb_init_fields", "hlb_set_state", "hlb_get_state",
            "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name",
-           "hlb_set_plan", "hlb_get_plan", "hlb_autotune", "hlb_last_error", "hlb_destroy", "hlb_version")
+           "hlb_set_plan", "hlb_get_plan", "hlb_autotune", "hlb_last_error", "hlb_destroy", "hlb_version",
+           "hlb_batch_workspace_size", "hlb_batch_create", "hlb_batch_info", "hlb_batch_init_fields",
+           "hlb_batch_step", "hlb_batch_step_timed", "hlb_batch_set_plan", "hlb_batch_get_plan", "hlb_batch_autotune",
+           "hlb_batch_get_fields", "hlb_batch_reduce", "hlb_batch_last_error",
+           "hlb_batch_destroy")
 
 
 class HlbError(RuntimeError):
@@ -58,6 +62,7 @@ class Stats(ctypes.Structure):
 _lib = None
 _dp = ctypes.POINTER(ctypes.c_double)
 _vp = ctypes.c_void_p
+_ip = ctypes.POINTER(ctypes.c_int)
 
 
 def load():
@@ -91,6 +96,20 @@ def load():
         "hlb_last_error": (ctypes.c_char_p, [_vp]),
         "hlb_destroy": (st, [_vp]),
         "hlb_version": (ctypes.c_char_p, []),
+        "hlb_batch_workspace_size": (st, [ctypes.c_int, ctypes.c_int, _ip, _ip, ctypes.POINTER(ctypes.c_size_t)]),
+        "hlb_batch_create": (st, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _ip, _ip,
+                                  ctypes.POINTER(Params), _vp, ctypes.c_size_t, _vp]),
+        "hlb_batch_info": (st, [_vp, _ip, _ip, _ip]),
+        "hlb_batch_init_fields": (st, [_vp, ctypes.c_int, _dp, _dp, _dp]),
+        "hlb_batch_step": (st, [_vp, ctypes.c_longlong]),
+        "hlb_batch_step_timed": (st, [_vp, ctypes.c_longlong, _dp]),
+        "hlb_batch_set_plan": (st, [_vp, _ip]),
+        "hlb_batch_get_plan": (st, [_vp, _ip]),
+        "hlb_batch_autotune": (st, [_vp, _dp]),
+        "hlb_batch_get_fields": (st, [_vp, ctypes.c_int, _dp, _dp, _dp, _dp]),
+        "hlb_batch_reduce": (st, [_vp, ctypes.c_int, ctypes.POINTER(Stats)]),
+        "hlb_batch_last_error": (ctypes.c_char_p, [_vp]),
+        "hlb_batch_destroy": (st, [_vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -103,6 +122,12 @@ def load():
 def _check(status: int, ctx=None):
     if status != HLB_OK:
         msg = load().hlb_last_error(ctx).decode()
+        raise HlbError(status, msg)
+
+
+def _bcheck(status: int, batch=None):
+    if status != HLB_OK:
+        msg = load().hlb_batch_last_error(batch).decode()
         raise HlbError(status, msg)
 
 
@@ -283,4 +308,129 @@ class Sim:
                "status": status}
         if raise_on_error and status != HLB_OK:
             _check(status, self.ctx)
+        return out
+
+
+def _ints(vals):
+    return (ctypes.c_int * len(vals))(*[int(v) for v in vals])
+
+
+def batch_workspace_size(storage, shapes) -> int:
+    nx = _ints([s[1] for s in shapes])
+    ny = _ints([s[0] for s in shapes])
+    b = ctypes.c_size_t()
+    _bcheck(load().hlb_batch_workspace_size(_STORAGE[storage], len(shapes), nx, ny, ctypes.byref(b)))
+    return b.value
+
+
+class Batch:
+    """Independent periodic D2Q9 simulations advanced together.
+
+    ``shapes`` is a list of ``(ny, nx)``; ``params`` a list of dicts of
+    ``hlb_params`` fields, one per simulation (or one dict for all).
+    """
+
+    def __init__(self, shapes, params_list, storage="f32", stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("the HIP library needs a GPU")
+        self.lib = load()
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        if any(len(s) != 2 for s in self.shapes):
+            raise ValueError("batch shapes are (ny, nx)")
+        n = len(self.shapes)
+        if isinstance(params_list, dict):
+            params_list = [params_list] * n
+        if len(params_list) != n:
+            raise ValueError("one parameter set per simulation")
+        self.storage = _STORAGE[storage]
+        nx = _ints([s[1] for s in self.shapes])
+        ny = _ints([s[0] for s in self.shapes])
+        nbytes = batch_workspace_size(storage, self.shapes)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._params = (Params * n)(*[params(**kw) for kw in params_list])
+        b = _vp()
+        _bcheck(self.lib.hlb_batch_create(ctypes.byref(b), self.storage, n, nx, ny, self._params,
+                                          ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                          ctypes.c_void_p(self.stream.cuda_stream)))
+        self.b = b
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def close(self):
+        if getattr(self, "b", None):
+            self.lib.hlb_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def m(self):
+        ms = (ctypes.c_int * len(self))()
+        _bcheck(self.lib.hlb_batch_info(self.b, None, None, ms), self.b)
+        return list(ms)
+
+    @property
+    def max_m(self) -> int:
+        v = ctypes.c_int()
+        _bcheck(self.lib.hlb_batch_info(self.b, None, ctypes.byref(v), None), self.b)
+        return v.value
+
+    def init(self, sim: int, phi, n=None, u=None):
+        shape = self.shapes[sim]
+        phi = _f64(phi, shape)
+        n = None if n is None else _f64(n, shape)
+        u = None if u is None else _f64(u, (2,) + shape)
+        _bcheck(self.lib.hlb_batch_init_fields(self.b, int(sim), _ptr(phi), _ptr(n), _ptr(u)), self.b)
+        return self
+
+    def step(self, nsteps: int = 1):
+        _bcheck(self.lib.hlb_batch_step(self.b, int(nsteps)), self.b)
+        return self
+
+    def step_timed(self, nsteps: int):
+        ms = (ctypes.c_double * 2)()
+        _bcheck(self.lib.hlb_batch_step_timed(self.b, int(nsteps), ms), self.b)
+        return float(ms[0]), float(ms[1])
+
+    @property
+    def plan(self):
+        """Tile shapes (lb_x, lb_y, substep_x, substep_y)."""
+        pl = (ctypes.c_int * 4)()
+        _bcheck(self.lib.hlb_batch_get_plan(self.b, pl), self.b)
+        return tuple(pl)
+
+    def set_plan(self, lb: int, ch: int):
+        pl = (ctypes.c_int * 2)(lb, ch)
+        _bcheck(self.lib.hlb_batch_set_plan(self.b, pl), self.b)
+
+    def autotune(self):
+        us = (ctypes.c_double * 2)()
+        _bcheck(self.lib.hlb_batch_autotune(self.b, us), self.b)
+        return float(us[0]), float(us[1])
+
+    def fields(self, sim: int):
+        shape = self.shapes[sim]
+        n = np.empty(shape)
+        u = np.empty((2,) + shape)
+        phi = np.empty(shape)
+        mu = np.empty(shape)
+        _bcheck(self.lib.hlb_batch_get_fields(self.b, int(sim), _ptr(n), _ptr(u), _ptr(phi), _ptr(mu)), self.b)
+        return {"n": n, "u": u, "phi": phi, "mu": mu}
+
+    def reduce(self, sim: int, raise_on_error: bool = True):
+        s = Stats()
+        status = self.lib.hlb_batch_reduce(self.b, int(sim), ctypes.byref(s))
+        out = {"mass": s.mass, "phi_sum": s.phi_sum, "kinetic": s.kinetic, "umax": s.umax,
+               "mom": np.array(list(s.mom)[:2]), "step": s.step, "finite": bool(s.finite),
+               "status": status}
+        if raise_on_error and status != HLB_OK:
+            _bcheck(status, self.b)
         return out

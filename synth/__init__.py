@@ -92,3 +92,31 @@ def uniform_velocity(shape, vel) -> np.ndarray:
     for k in range(d):
         u[k] = vel[k]
     return u
+
+
+def batch_specs(nsim: int, seed: int, lmin: int = 64, lmax: int = 256):
+    """Draws a batch of independent drop / flat-interface simulations.
+
+    Simulation b has a square periodic lattice of side L ~ U{lmin..lmax}
+    (integers), kappa ~ U(0.05, 0.2), tau ~ U(0.6, 1.5) and, with equal
+    probability, either a drop of radius R ~ U(8, L/4) at a uniformly drawn
+    centre or a slab with two flat interfaces, normal to x or y, of thickness
+    ~ U(L/4, 3L/4) at a uniformly drawn offset.  Returns a list of dicts
+    ``{"shape", "kappa", "tau", "kind", "radius", "center", "x0", "x1",
+    "axis"}``; the caller turns a spec into phi with ``drop`` or ``slab``
+    and the interface width of its own free energy.
+    """
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(int(nsim)):
+        L = int(rng.integers(lmin, lmax + 1))
+        spec = {"shape": (L, L), "kappa": float(rng.uniform(0.05, 0.2)), "tau": float(rng.uniform(0.6, 1.5))}
+        if rng.uniform() < 0.5:
+            spec.update(kind="drop", radius=float(rng.uniform(8.0, L / 4.0)),
+                        center=(float(rng.uniform(0, L)), float(rng.uniform(0, L))))
+        else:
+            thick = float(rng.uniform(L / 4.0, 3.0 * L / 4.0))
+            x0 = float(rng.uniform(0, L - thick))
+            spec.update(kind="slab", x0=x0, x1=x0 + thick, axis=int(rng.choice([-1, -2])))
+        out.append(spec)
+    return out

@@ -101,3 +101,36 @@ def test_create_rejects_before_touching_the_device(hlb):
     st = lib.hlb_create(ctypes.byref(ctx), 0, 1, 16, 16, 1, ctypes.byref(p), None, 0, None)
     assert st == hlb.HLB_EINVAL
     assert b"tau" in lib.hlb_last_error(None)
+
+
+def test_batch_workspace_size_and_shape_errors(hlb):
+    shapes = [(64, 64), (96, 128), (7, 5)]
+    b = hlb.batch_workspace_size("f32", shapes)
+    sites = sum(ny * nx for ny, nx in shapes)
+    # per simulation: two population copies, two phi and u*, all float
+    assert b >= (2 * 9 + 2 + 2) * 4 * sites
+    assert hlb.batch_workspace_size("f64", shapes) > b
+    for bad in ([(0, 4)], [(4, 4), (4, -2)]):
+        with pytest.raises(hlb.HlbError) as e:
+            hlb.batch_workspace_size("f32", bad)
+        assert e.value.status == hlb.HLB_ESHAPE
+    with pytest.raises(hlb.HlbError) as e:
+        hlb.batch_workspace_size("f32", [])
+    assert e.value.status == hlb.HLB_EINVAL
+
+
+def test_batch_create_rejects_before_touching_the_device(hlb):
+    """A batch names the simulation whose parameters are invalid, and a
+    missing workspace is rejected, all on the host."""
+    lib = hlb.load()
+    b = ctypes.c_void_p()
+    nx = (ctypes.c_int * 2)(16, 32)
+    ny = (ctypes.c_int * 2)(16, 8)
+    ps = (hlb.Params * 2)(hlb.params(), hlb.params(tau=0.4))
+    st = lib.hlb_batch_create(ctypes.byref(b), 1, 2, nx, ny, ps, None, 0, None)
+    assert st == hlb.HLB_EINVAL and not b.value
+    assert b"simulation 1" in lib.hlb_batch_last_error(None)
+    ps[1] = hlb.params()
+    st = lib.hlb_batch_create(ctypes.byref(b), 1, 2, nx, ny, ps, None, 0, None)
+    assert st == hlb.HLB_ESHAPE and not b.value
+    assert b"workspace" in lib.hlb_batch_last_error(None)
