@@ -199,28 +199,37 @@ def run_gpu_batch(name, steps, warmup, plan=None):
     stats = [batch.reduce(i, raise_on_error=False) for i in range(len(shapes))]
     tile_plan = batch.plan
     batch.close()
+    kind, fuse = tile_plan[2], tile_plan[3]
     lb_b, ch_b, step_b = algorithmic_bytes(2, 9, es)
+    # a substep launch reads phi and u* and writes phi once per site of the
+    # simulations it covers, however many substeps it fuses
+    launch_sites = sum(n * -(-m // fuse) for n, m in zip(ns, ms))
+    nlaunch = -(-max(ms) // fuse)
     t_lb = ms_lb / nprof * 1e-3                 # s per collide-and-stream launch
     t_ch_step = ms_ch / nprof * 1e-3            # s of substep launches per step
-    max_m = max(ms)
-    t_ch = t_ch_step / max_m                    # s per substep launch (average)
+    t_ch = t_ch_step / nlaunch                  # s per substep launch (average)
     lb_gbs = lb_b * total / t_lb / 1e9
-    ch_gbs = ch_b * sub_sites / t_ch_step / 1e9  # bytes of all substeps of a step over their time
+    ch_gbs = ch_b * launch_sites / t_ch_step / 1e9
     dominant = "lb" if t_lb > t_ch_step else "ch"
-    lbname = f"hlb::k_lb_batch<float, {tile_plan[0]}, {tile_plan[1]}>"
-    chname = f"hlb::k_ch_batch<float, {tile_plan[2]}, {tile_plan[3]}, true>"
+    tname = "float" if storage == "f32" else "double"
+    lbname = f"hlb::k_lb_batch<{tname}, {tile_plan[0]}, {tile_plan[1]}>"
+    chname = {0: f"hlb::k_ch_batch<{tname}, {tile_plan[4]}, {tile_plan[5]}, true>",
+              1: f"hlb::k_chf_batch<{tname}, {fuse}, {tile_plan[4]}, true>",
+              2: f"hlb::k_chm_batch<{tname}, {fuse}, {tile_plan[4]}>"}[kind]
     kd = ({"name": lbname, "bytes_per_lu": lb_b, "gbs": lb_gbs, "units": total} if dominant == "lb" else
-          {"name": chname + f" (class average over {max_m} launches per step)", "bytes_per_lu": ch_b,
-           "gbs": ch_gbs, "units": sub_sites / max_m})
+          {"name": chname + f" (class average over {nlaunch} launches per step)", "bytes_per_lu": ch_b,
+           "gbs": ch_gbs, "units": launch_sites / nlaunch})
     return {
-        "shape": None, "storage": storage, "desc": desc, "m": f"{min(ms)}..{max_m} (mean {sub_sites / total:.2f})",
+        "shape": None, "storage": storage, "desc": desc, "m": f"{min(ms)}..{max(ms)} (mean {sub_sites / total:.2f})",
         "ns": total, "secs": secs, "mlups": total * steps / secs / 1e6, "mlups_standard": None,
         "stats": {"finite": all(s["finite"] for s in stats), "mass": sum(s["mass"] for s in stats),
-                  "umax": max(s["umax"] for s in stats)},
+                  "umax": max(s["umax"] for s in stats),
+                  "umax_sim": max(range(len(stats)), key=lambda i: stats[i]["umax"])},
         "plan": tile_plan,
         "kernels": {"lb": {"name": lbname, "us_per_launch": t_lb * 1e6, "bytes_per_lu": lb_b, "gbs": lb_gbs},
-                    "ch": {"name": chname, "us_per_launch": t_ch * 1e6, "launches_per_step": max_m,
-                           "substep_site_updates_per_step": sub_sites, "bytes_per_lu": ch_b, "gbs": ch_gbs}},
+                    "ch": {"name": chname, "us_per_launch": t_ch * 1e6, "launches_per_step": nlaunch,
+                           "substeps_per_launch": fuse, "substep_site_updates_per_step": sub_sites,
+                           "launch_site_updates_per_step": launch_sites, "bytes_per_lu": ch_b, "gbs": ch_gbs}},
         "dominant": kd, "step_min_bytes_per_lu": step_b, "q": 9, "d": 2, "es": es,
         "nsim": len(shapes), "sites": total,
     }
@@ -364,7 +373,7 @@ def main():
         "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
         "mlups_standard_stencil": r["mlups_standard"],
         "kernels": r["kernels"],
-        "check": {"finite": r["stats"]["finite"], "mass": r["stats"]["mass"], "umax": r["stats"]["umax"]},
+        "check": {k: r["stats"][k] for k in ("finite", "mass", "umax", "umax_sim") if k in r["stats"]},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

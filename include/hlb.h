@@ -273,20 +273,33 @@ hlb_status hlb_batch_step(hlb_batch *b, long long nsteps);
  * Synchronises. */
 hlb_status hlb_batch_step_timed(hlb_batch *b, long long nsteps, double ms[2]);
 
-/* Tile shapes of the batch's two launches: plan[0] indexes the
- * collide-and-stream tiles {64x8, 32x8, 64x4, 32x16}, plan[1] the substep
- * tiles {64x8, 32x8, 64x16, 32x16} (x by y sites).  HLB_EINVAL out of range.
- * Rebuilds the tile tables and synchronises. */
+/* Tile shapes of the batch's launches.  plan[0] indexes the
+ * collide-and-stream tiles {64x8, 32x8, 64x4, 32x16} (x by y sites).
+ * plan[1] indexes the substep launches (Sec. 2.3's substeps):
+ *   0-3   one substep per launch on tiles {64x8, 32x8, 64x16, 32x16};
+ *   4     2 substeps fused in LDS on 32x32 tiles (HLB_F32_SHIFTED) or
+ *         16x16 tiles (HLB_F64);
+ *   5-11  a march along y of blocks of (columns, rows per segment) fusing
+ *         f substeps, (f, columns, rows) = (1, 64, 32), (1, 64, 64),
+ *         (1, 128, 32), (1, 128, 64), (1, 256, 32), (2, 128, 32),
+ *         (2, 128, 64); the march needs cd_Q = 1 in every simulation (else
+ *         HLB_EINVAL).
+ * A step has ceil(max_b m_b / f) substep launches (f = 1 for 0-3); a
+ * simulation with fewer substeps left than f in its last launch does only
+ * those.  HLB_EINVAL out of range.  The state is kept.  Rebuilds the tile
+ * tables and synchronises. */
 hlb_status hlb_batch_set_plan(hlb_batch *b, const int plan[2]);
 
-/* The current tile shapes: plan = {lb_x, lb_y, substep_x, substep_y}. */
-hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[4]);
+/* The current plan as plan = {lb_x, lb_y, substep kind (0 tiles, 1 fused
+ * tiles, 2 march), substeps per launch, substep x, substep y}; for a march,
+ * x is the block's columns and y its rows per segment. */
+hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[6]);
 
-/* Times every candidate tile shape of both launches on the current state
- * (the timed launches write only buffers that are not state between steps,
- * so the state is unchanged), keeps the fastest of each and writes their
- * times in microseconds per launch to us[0] (collide-and-stream) and us[1]
- * (one substep over every simulation); us may be NULL.  Synchronises. */
+/* Times every candidate of both launch classes on the current state (the
+ * timed launches write only buffers that are not state between steps, so
+ * the state is unchanged), keeps the fastest of each and writes their times
+ * in microseconds to us[0] (one collide-and-stream launch) and us[1] (the
+ * substep launches of one step); us may be NULL.  Synchronises. */
 hlb_status hlb_batch_autotune(hlb_batch *b, double us[2]);
 
 /* Moments of simulation sim, as hlb_get_fields (2D: u has 2*ns values).

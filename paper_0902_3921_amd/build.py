@@ -20,6 +20,8 @@ FLAGS = [
     # does not know the feature; harmless)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
+    # an undefined symbol fails the link, not the first load of the library
+    "-Wl,-z,defs",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
 ]
 

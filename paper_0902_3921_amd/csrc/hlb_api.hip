@@ -1050,11 +1050,38 @@ namespace {
 struct TileShape {
   int x, y;
 };
-// candidate tile shapes (256 threads per block)
+struct ChShape {
+  int kind;  // 0: tiles, one substep per launch; 1: tiles, fuse substeps in LDS; 2: y-march
+  int fuse;  // substeps per launch
+  int x, y;  // tile (kinds 0, 1); threads = columns per block and rows per segment (kind 2)
+};
+// Candidate substep launches.  Kind 0 runs one substep per launch on x by y
+// tiles (k_ch_batch); kind 1 fuses `fuse` substeps of a square tile in LDS
+// (k_chf_batch, sized so the static LDS stays < 64 KiB); kind 2 marches
+// x consecutive columns along y over segments of y rows, fusing `fuse`
+// substeps (k_chm_batch; standard 5-point Laplacian only).
 constexpr TileShape kBatchLB[] = {{64, 8}, {32, 8}, {64, 4}, {32, 16}};
-constexpr TileShape kBatchCH[] = {{64, 8}, {32, 8}, {64, 16}, {32, 16}};
+template <typename T> struct BatchCH;
+template <> struct BatchCH<float> {
+  static constexpr ChShape c[] = {{0, 1, 64, 8},  {0, 1, 32, 8},   {0, 1, 64, 16}, {0, 1, 32, 16},
+                                  {1, 2, 32, 32}, {2, 1, 64, 32},  {2, 1, 64, 64}, {2, 1, 128, 32},
+                                  {2, 1, 128, 64}, {2, 1, 256, 32}, {2, 2, 128, 32}, {2, 2, 128, 64}};
+};
+template <> struct BatchCH<double> {
+  static constexpr ChShape c[] = {{0, 1, 64, 8},  {0, 1, 32, 8},   {0, 1, 64, 16}, {0, 1, 32, 16},
+                                  {1, 2, 16, 16}, {2, 1, 64, 32},  {2, 1, 64, 64}, {2, 1, 128, 32},
+                                  {2, 1, 128, 64}, {2, 1, 256, 32}, {2, 2, 128, 32}, {2, 2, 128, 64}};
+};
 constexpr int kNumLB = sizeof(kBatchLB) / sizeof(kBatchLB[0]);
-constexpr int kNumCH = sizeof(kBatchCH) / sizeof(kBatchCH[0]);
+constexpr int kNumCH = 12;
+static_assert(sizeof(BatchCH<float>::c) / sizeof(ChShape) == kNumCH, "candidate count");
+static_assert(sizeof(BatchCH<double>::c) / sizeof(ChShape) == kNumCH, "candidate count");
+
+// output columns of a march block, and the tile of a candidate in sites
+int march_cols(const ChShape &c) { return c.x - 6 * c.fuse; }
+TileShape ch_tile_sites(const ChShape &c) { return c.kind == 2 ? TileShape{march_cols(c), c.y} : TileShape{c.x, c.y}; }
+
+ChShape ch_shape(int storage, int i) { return storage == HLB_F64 ? BatchCH<double>::c[i] : BatchCH<float>::c[i]; }
 
 }  // namespace
 
@@ -1071,7 +1098,14 @@ struct hlb_batch {
   int max_m;
   int lb_plan, ch_plan;       // indices into the candidate tile shapes
   int nlb;                    // blocks of the collide-and-stream launch
-  std::vector<int> nch;       // blocks of substep launch s
+  struct ChLaunch {
+    const void *fn;  // kernel
+    int off, nblk;   // tile table range
+    int threads, j;  // block size, substep launch of the step
+  };
+  std::vector<ChLaunch> ch;   // the substep launches of a step, in order
+  int nlaunch;                // substep launches per step (ceil(max_m / fuse))
+  std::vector<SimDesc> desc;  // host copy of the device descriptors
   int par;                    // step parity
   long long step;
   hipGraphExec_t exec[2];
@@ -1120,7 +1154,8 @@ BatchLayout batch_layout(int storage, int nsim, const int *nx, const int *ny) {
     max_part = std::max(max_part, ceil_div(nx[i], rtx) * ceil_div(ny[i], rty));
   }
   for (auto t : kBatchLB) max_lb = std::max(max_lb, count_tiles(nsim, nx, ny, t));
-  for (auto t : kBatchCH) max_ch = std::max(max_ch, count_tiles(nsim, nx, ny, t));
+  for (int c = 0; c < kNumCH; c++)
+    max_ch = std::max(max_ch, count_tiles(nsim, nx, ny, ch_tile_sites(ch_shape(storage, c))));
   size_t off = 0;
   L.desc = off;
   off = align_up(off + sizeof(SimDesc) * nsim);
@@ -1154,11 +1189,14 @@ hlb_status batch_shapes(int nsim, const int *nx, const int *ny, std::string *msg
       *msg = "every simulation needs nx, ny >= 1 and nx*ny < 2^31";
       return HLB_ESHAPE;
     }
-  for (auto t : kBatchLB)
-    if (count_tiles(nsim, nx, ny, t) < 0) {
-      *msg = "too many tiles in the batch (more than 2^30)";
-      return HLB_ESHAPE;
-    }
+  bool over = false;
+  for (auto t : kBatchLB) over = over || count_tiles(nsim, nx, ny, t) < 0;
+  for (int c = 0; c < kNumCH; c++)
+    for (int st : {HLB_F64, HLB_F32_SHIFTED}) over = over || count_tiles(nsim, nx, ny, ch_tile_sites(ch_shape(st, c))) < 0;
+  if (over) {
+    *msg = "too many tiles in the batch (more than 2^30)";
+    return HLB_ESHAPE;
+  }
   return HLB_OK;
 }
 
@@ -1167,22 +1205,68 @@ T *bat(hlb_batch *b, size_t off) {
   return reinterpret_cast<T *>(b->ws + off);
 }
 
-// Tile tables of the current plan, copied to the device; blocks per launch.
-hlb_status batch_tables(hlb_batch *b) {
-  const TileShape tl = kBatchLB[b->lb_plan], tc = kBatchCH[b->ch_plan];
+const void *ch_fn(const hlb_batch *b, const ChShape &c, int r);
+const void *lb_fn(const hlb_batch *b, int plan);
+
+// Switches to plan (lb, ch): tile tables, the substep launches of a step and
+// the descriptors' launch counts, copied to the device.  A simulation's phi
+// stays in the buffer it is in: its phibase is chosen so that the parity
+// rule of the new launch count names the same buffer.  The substep table
+// lists the simulations in decreasing m, so the simulations that launch j
+// touches are a prefix of it, and, for a march, those with r = min(fuse,
+// m - j fuse) substeps left in launch j are a contiguous run inside it.
+hlb_status batch_tables(hlb_batch *b, int lb, int ch) {
+  const TileShape tl = kBatchLB[lb];
+  const ChShape tc = ch_shape(b->storage, ch);
+  const TileShape ts = ch_tile_sites(tc);
+  for (int i = 0; i < b->nsim; i++) {
+    SimDesc &d = b->desc[i];
+    const int cur = d.phibase ^ (b->par & d.nl & 1);
+    d.nl = ceil_div(b->m[i], tc.fuse);
+    d.phibase = cur ^ (b->par & d.nl & 1);
+  }
   std::vector<TileRef> lbt, cht;
   for (int i = 0; i < b->nsim; i++)
     for (int y = 0; y < b->ny[i]; y += tl.y)
       for (int x = 0; x < b->nx[i]; x += tl.x) lbt.push_back(TileRef{i, x, y, 0});
-  b->nch.assign(b->max_m, 0);
+  std::vector<int> first(b->nsim), count(b->nsim);  // table range of each simulation
   for (int i : b->order) {
-    for (int y = 0; y < b->ny[i]; y += tc.y)
-      for (int x = 0; x < b->nx[i]; x += tc.x) cht.push_back(TileRef{i, x, y, 0});
-    for (int s = 0; s < b->m[i]; s++) b->nch[s] = (int)cht.size();
+    first[i] = (int)cht.size();
+    for (int y = 0; y < b->ny[i]; y += ts.y)
+      for (int x = 0; x < b->nx[i]; x += ts.x) cht.push_back(TileRef{i, x, y, 0});
+    count[i] = (int)cht.size() - first[i];
+  }
+  b->nlaunch = ceil_div(b->max_m, tc.fuse);
+  b->ch.clear();
+  const int threads = tc.kind == 2 ? tc.x : NT;
+  for (int j = 0; j < b->nlaunch; j++) {
+    // runs of simulations (in table order) by substeps left in launch j
+    int run_r = 0, run_off = 0, run_n = 0;
+    auto flush = [&]() {
+      if (run_n > 0) b->ch.push_back({ch_fn(b, tc, run_r), run_off, run_n, threads, j});
+      run_n = 0;
+    };
+    for (int i : b->order) {
+      const int left = b->m[i] - j * tc.fuse;
+      if (left <= 0) break;  // decreasing m: no later simulation is touched
+      const int r = tc.kind == 2 ? std::min(tc.fuse, left) : tc.fuse;
+      if (run_n == 0 || r != run_r) {
+        flush();
+        run_r = r;
+        run_off = first[i];
+      }
+      run_n += count[i];
+    }
+    flush();
   }
   b->nlb = (int)lbt.size();
-  hipError_t e = hipMemcpyAsync(b->ws + b->lbt_off, lbt.data(), sizeof(TileRef) * lbt.size(), hipMemcpyHostToDevice,
-                                b->stream);
+  b->lb_plan = lb;
+  b->ch_plan = ch;
+  hipError_t e = hipMemcpyAsync(b->ws + b->desc_off, b->desc.data(), sizeof(SimDesc) * b->nsim,
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->ws + b->lbt_off, lbt.data(), sizeof(TileRef) * lbt.size(), hipMemcpyHostToDevice,
+                       b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->ws + b->cht_off, cht.data(), sizeof(TileRef) * cht.size(), hipMemcpyHostToDevice,
                        b->stream);
@@ -1209,22 +1293,44 @@ const void *lb_fn_i(int i) {
 }
 
 template <typename T, int I>
-const void *ch_fn_i(int i, bool lap5) {
+const void *ch_fn_i(int i, int r, bool lap5) {
   if constexpr (I == kNumCH) {
     return nullptr;
   } else {
-    if (i == I)
-      return lap5 ? reinterpret_cast<const void *>(&k_ch_batch<T, kBatchCH[I].x, kBatchCH[I].y, true>)
-                  : reinterpret_cast<const void *>(&k_ch_batch<T, kBatchCH[I].x, kBatchCH[I].y, false>);
-    return ch_fn_i<T, I + 1>(i, lap5);
+    constexpr ChShape c = BatchCH<T>::c[I];
+    if (i != I) return ch_fn_i<T, I + 1>(i, r, lap5);
+    if constexpr (c.kind == 0)
+      return lap5 ? reinterpret_cast<const void *>(&k_ch_batch<T, c.x, c.y, true>)
+                  : reinterpret_cast<const void *>(&k_ch_batch<T, c.x, c.y, false>);
+    else if constexpr (c.kind == 1)
+      return lap5 ? reinterpret_cast<const void *>(&k_chf_batch<T, c.fuse, c.x, true>)
+                  : reinterpret_cast<const void *>(&k_chf_batch<T, c.fuse, c.x, false>);
+    else {
+      // a march fusing r <= fuse substeps (the table is blocked for fuse)
+      static_assert(c.fuse >= 1 && c.fuse <= 3, "march fuse");
+      static_assert(c.x - 6 * c.fuse > 0, "march block narrower than its halo");
+      if (r == 3) return reinterpret_cast<const void *>(&k_chm_batch<T, (c.fuse >= 3 ? 3 : 1), c.x>);
+      if (r == 2) return reinterpret_cast<const void *>(&k_chm_batch<T, (c.fuse >= 2 ? 2 : 1), c.x>);
+      return reinterpret_cast<const void *>(&k_chm_batch<T, 1, c.x>);
+    }
   }
 }
 
 const void *lb_fn(const hlb_batch *b, int plan) {
   return b->storage == HLB_F64 ? lb_fn_i<double, 0>(plan) : lb_fn_i<float, 0>(plan);
 }
-const void *ch_fn(const hlb_batch *b, int plan) {
-  return b->storage == HLB_F64 ? ch_fn_i<double, 0>(plan, b->lap5) : ch_fn_i<float, 0>(plan, b->lap5);
+
+int ch_index(int storage, const ChShape &c) {
+  for (int i = 0; i < kNumCH; i++) {
+    const ChShape d = ch_shape(storage, i);
+    if (d.kind == c.kind && d.fuse == c.fuse && d.x == c.x && d.y == c.y) return i;
+  }
+  return -1;
+}
+
+const void *ch_fn(const hlb_batch *b, const ChShape &c, int r) {
+  const int i = ch_index(b->storage, c);
+  return b->storage == HLB_F64 ? ch_fn_i<double, 0>(i, r, b->lap5) : ch_fn_i<float, 0>(i, r, b->lap5);
 }
 
 // Launch arguments of the two batch kernels (the pointers are typed by the
@@ -1248,15 +1354,18 @@ struct ChArgs {
   const void *sims, *tiles;
   void *phi;
   const void *u;
-  int par, s;
-  void *slot[6];
+  int par, j, jpar, seg, ncol;
+  void *slot[9];
   void **bind() {
     slot[0] = &sims;
     slot[1] = &tiles;
     slot[2] = &phi;
     slot[3] = &u;
     slot[4] = &par;
-    slot[5] = &s;
+    slot[5] = &j;
+    slot[6] = &jpar;
+    slot[7] = &seg;
+    slot[8] = &ncol;
     return slot;
   }
 };
@@ -1264,22 +1373,35 @@ struct ChArgs {
 LbArgs lb_args(hlb_batch *b, int par) {
   return LbArgs{b->ws + b->desc_off, b->ws + b->lbt_off, b->ws + b->g_off, b->ws + b->phi_off, b->ws + b->u_off, par, {}};
 }
-ChArgs ch_args(hlb_batch *b, int par, int s) {
-  return ChArgs{b->ws + b->desc_off, b->ws + b->cht_off, b->ws + b->phi_off, b->ws + b->u_off, par, s, {}};
+// Arguments of substep launch k of a step; timing = true reads the state's
+// phi and writes the spare buffer whatever the launch is (the same work,
+// state unchanged).
+ChArgs ch_args(hlb_batch *b, int par, int k, bool timing) {
+  const hlb_batch::ChLaunch &L = b->ch[k];
+  const ChShape c = ch_shape(b->storage, b->ch_plan);
+  return ChArgs{b->ws + b->desc_off, b->ws + b->cht_off + sizeof(TileRef) * L.off, b->ws + b->phi_off,
+                b->ws + b->u_off, par, L.j, timing ? 0 : (L.j & 1), c.y, c.kind == 2 ? march_cols(c) : 0, {}};
 }
 
 hipError_t launch_lb(hlb_batch *b, int plan, int par) {
   LbArgs a = lb_args(b, par);
   return hipLaunchKernel(lb_fn(b, plan), dim3(b->nlb), dim3(NT), a.bind(), 0, b->stream);
 }
-hipError_t launch_ch(hlb_batch *b, int plan, int par, int s, int nblk) {
-  ChArgs a = ch_args(b, par, s);
-  return hipLaunchKernel(ch_fn(b, plan), dim3(nblk), dim3(NT), a.bind(), 0, b->stream);
+hipError_t launch_ch(hlb_batch *b, int par, int k, bool timing = false) {
+  ChArgs a = ch_args(b, par, k, timing);
+  const hlb_batch::ChLaunch &L = b->ch[k];
+  return hipLaunchKernel(L.fn, dim3(L.nblk), dim3(L.threads), a.bind(), 0, b->stream);
+}
+
+hipError_t launch_ch_all(hlb_batch *b, int par, bool timing = false) {
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < (int)b->ch.size() && e == hipSuccess; k++) e = launch_ch(b, par, k, timing);
+  return e;
 }
 
 hipError_t batch_enqueue_step(hlb_batch *b, int par) {
   hipError_t e = launch_lb(b, b->lb_plan, par);
-  for (int s = 0; s < b->max_m && e == hipSuccess; s++) e = launch_ch(b, b->ch_plan, par, s, b->nch[s]);
+  if (e == hipSuccess) e = launch_ch_all(b, par);
   return e;
 }
 
@@ -1301,12 +1423,12 @@ hlb_status batch_build_graph(hlb_batch *b, int par, hipGraphExec_t *exec) {
     hipGraphNode_t node;
     e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
     if (e == hipSuccess) prev = node;
-    for (int s = 0; s < b->max_m && e == hipSuccess; s++) {
-      ChArgs ca = ch_args(b, pp, s);
+    for (int k = 0; k < (int)b->ch.size() && e == hipSuccess; k++) {
+      ChArgs ca = ch_args(b, pp, k, false);
       hipKernelNodeParams kc{};
-      kc.func = const_cast<void *>(ch_fn(b, b->ch_plan));
-      kc.gridDim = dim3(b->nch[s]);
-      kc.blockDim = dim3(NT);
+      kc.func = const_cast<void *>(b->ch[k].fn);
+      kc.gridDim = dim3(b->ch[k].nblk);
+      kc.blockDim = dim3(b->ch[k].threads);
       kc.kernelParams = ca.bind();
       e = hipGraphAddKernelNode(&node, graph, &prev, 1, &kc);
       if (e == hipSuccess) prev = node;
@@ -1338,7 +1460,8 @@ void sim_state(hlb_batch *b, int i, T **g, T **phi) {
   const size_t ns = (size_t)b->nx[i] * b->ny[i];
   const size_t gstride = ((9 * ns + 63) / 64) * 64, pstride = ((ns + 63) / 64) * 64;
   *g = bat<T>(b, b->g_off) + b->g_el[i] + (b->par ? gstride : 0);
-  *phi = bat<T>(b, b->phi_off) + b->phi_el[i] + ((b->par & b->m[i] & 1) ? pstride : 0);
+  const SimDesc &d = b->desc[i];
+  *phi = bat<T>(b, b->phi_off) + b->phi_el[i] + ((d.phibase ^ (b->par & d.nl & 1)) ? pstride : 0);
 }
 
 template <typename T>
@@ -1437,7 +1560,8 @@ hlb_status hlb_batch_create(hlb_batch **out, int storage, int nsim, const int *n
   b->par = 0;
   b->step = 0;
   b->have_exec[0] = b->have_exec[1] = false;
-  std::vector<SimDesc> desc(nsim);
+  std::vector<SimDesc> &desc = b->desc;
+  desc.resize(nsim);
   for (int i = 0; i < nsim; i++) {
     const long long ns = (long long)nx[i] * ny[i];
     desc[i].p = make_kparams(2, nx[i], ny[i], 1, params[i], ms[i]);
@@ -1447,14 +1571,11 @@ hlb_status hlb_batch_create(hlb_batch **out, int storage, int nsim, const int *n
     desc[i].phi[1] = L.phi_el[i] + ((ns + 63) / 64) * 64;
     desc[i].u = L.u_el[i];
     desc[i].m = ms[i];
+    desc[i].nl = ms[i];
+    desc[i].phibase = 0;
     desc[i].pad = 0;
   }
-  hipError_t e = hipMemcpyAsync(b->ws + L.desc, desc.data(), sizeof(SimDesc) * nsim, hipMemcpyHostToDevice, b->stream);
-  if (e != hipSuccess) {
-    delete b;
-    return bfail(nullptr, HLB_EHIP, std::string("batch descriptors: ") + hipGetErrorString(e));
-  }
-  s = batch_tables(b);
+  s = batch_tables(b, 0, 0);
   if (s != HLB_OK) {
     g_batch_error = b->err;
     delete b;
@@ -1538,7 +1659,7 @@ hlb_status hlb_batch_step_timed(hlb_batch *b, long long nsteps, double ms[2]) {
       e = hipEventRecord(ev[3 * t], b->stream);
       if (e == hipSuccess) e = launch_lb(b, b->lb_plan, b->par);
       if (e == hipSuccess) e = hipEventRecord(ev[3 * t + 1], b->stream);
-      for (int s = 0; s < b->max_m && e == hipSuccess; s++) e = launch_ch(b, b->ch_plan, b->par, s, b->nch[s]);
+      if (e == hipSuccess) e = launch_ch_all(b, b->par);
       if (e == hipSuccess) e = hipEventRecord(ev[3 * t + 2], b->stream);
       if (e == hipSuccess) {
         b->par ^= 1;
@@ -1566,17 +1687,20 @@ hlb_status hlb_batch_set_plan(hlb_batch *b, const int plan[2]) {
   if (!b || !plan) return HLB_EINVAL;
   if (plan[0] < 0 || plan[0] >= kNumLB || plan[1] < 0 || plan[1] >= kNumCH)
     return bfail(b, HLB_EINVAL, "plan indices out of range");
-  b->lb_plan = plan[0];
-  b->ch_plan = plan[1];
-  return batch_tables(b);
+  if (ch_shape(b->storage, plan[1]).kind == 2 && !b->lap5)
+    return bfail(b, HLB_EINVAL, "march plans need the 5-point Laplacian (cd_Q = 1) in every simulation");
+  return batch_tables(b, plan[0], plan[1]);
 }
 
-hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[4]) {
+hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[6]) {
   if (!b || !plan) return HLB_EINVAL;
+  const ChShape c = ch_shape(b->storage, b->ch_plan);
   plan[0] = kBatchLB[b->lb_plan].x;
   plan[1] = kBatchLB[b->lb_plan].y;
-  plan[2] = kBatchCH[b->ch_plan].x;
-  plan[3] = kBatchCH[b->ch_plan].y;
+  plan[2] = c.kind;
+  plan[3] = c.fuse;
+  plan[4] = c.x;
+  plan[5] = c.y;
   return HLB_OK;
 }
 
@@ -1594,22 +1718,25 @@ hlb_status hlb_batch_autotune(hlb_batch *b, double us[2]) {
   hlb_status st = HLB_OK;
   // The collide-and-stream kernel reads populations[par] and phi and writes
   // the other population buffer and u*, neither of which is state between
-  // steps; substep 0 reads phi and u* and writes the spare phi buffer.  So
-  // timing either leaves the state as it was.  Each class is timed with the
-  // best shape of the classes before it.
+  // steps.  The substep launches of a step are timed in their timing form:
+  // each reads the state's phi and u* and writes the spare phi buffer, with
+  // the blocks and substeps of the real launch.  So the state is unchanged.
+  // The substep candidates are timed with the best collide-and-stream shape.
   for (int cls = 0; cls < 2 && st == HLB_OK; cls++) {
     const int ncand = cls == 0 ? kNumLB : kNumCH;
     for (int c = 0; c < ncand && st == HLB_OK; c++) {
-      if (cls == 0) b->lb_plan = c;
-      else b->ch_plan = c;
-      st = batch_tables(b);
+      if (cls == 1 && ch_shape(b->storage, c).kind == 2 && !b->lap5) continue;
+      st = cls == 0 ? batch_tables(b, c, pick[1]) : batch_tables(b, pick[0], c);
       if (st != HLB_OK) break;
       // the first launch (untimed) gives u* its values for the substeps
       hipError_t e = launch_lb(b, b->lb_plan, b->par);
       for (int r = 0; r < 1 + REPS && e == hipSuccess; r++) {
         if (r == 1) e = hipEventRecord(e0, b->stream);
-        if (e != hipSuccess) break;
-        e = cls == 0 ? launch_lb(b, b->lb_plan, b->par) : launch_ch(b, b->ch_plan, b->par, 0, b->nch[0]);
+        if (cls == 0) {
+          if (e == hipSuccess) e = launch_lb(b, b->lb_plan, b->par);
+        } else {
+          if (e == hipSuccess) e = launch_ch_all(b, b->par, true);
+        }
       }
       if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
@@ -1625,14 +1752,11 @@ hlb_status hlb_batch_autotune(hlb_batch *b, double us[2]) {
         pick[cls] = c;
       }
     }
-    if (cls == 0) b->lb_plan = pick[0];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != HLB_OK) return st;
-  b->lb_plan = pick[0];
-  b->ch_plan = pick[1];
-  st = batch_tables(b);
+  st = batch_tables(b, pick[0], pick[1]);
   if (st != HLB_OK) return st;
   if (us) {
     us[0] = best[0];

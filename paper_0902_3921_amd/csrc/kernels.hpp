@@ -517,6 +517,8 @@ struct SimDesc {
   long long phi[2];     // element offsets of the two phi buffers
   long long u;          // element offset of u*
   int m;                // convection-diffusion substeps per step
+  int nl;               // substep launches per step that touch this simulation
+  int phibase;          // phi buffer at the start of an even step
   int pad;
 };
 
@@ -525,10 +527,10 @@ struct TileRef {
 };
 
 // Batched simulations share one step parity `par` (steps since the start,
-// mod 2): populations are read from buffer par and written to 1 - par; a
-// simulation's phi starts step t in buffer (t m) mod 2 = par & m & 1, since
-// each of its m substeps flips it.
-__device__ __forceinline__ int batch_phi_buf(int par, int m) { return par & m & 1; }
+// mod 2): populations are read from buffer par and written to 1 - par.  Each
+// substep launch that touches a simulation flips its phi buffer, nl times a
+// step, so a simulation's phi starts a step in buffer phibase ^ (par & nl & 1).
+__device__ __forceinline__ int batch_phi_buf(const SimDesc &sd, int par) { return sd.phibase ^ (par & sd.nl & 1); }
 
 template <typename T, int TX, int TY>
 __global__ void __launch_bounds__(NT) k_lb_batch(const SimDesc *__restrict__ sims, const TileRef *__restrict__ tiles,
@@ -536,23 +538,120 @@ __global__ void __launch_bounds__(NT) k_lb_batch(const SimDesc *__restrict__ sim
   int b, unused1, unused2;
   tile_coords(b, unused1, unused2);
   const TileRef tr = tiles[b];
-  const SimDesc sd = sims[tr.sim];
-  lb_tile<D2Q9, T, TX, TY, 1>(sd.p, g + sd.g[par], g + sd.g[1 - par], phi + sd.phi[batch_phi_buf(par, sd.m)],
+  const SimDesc &sd = sims[tr.sim];  // read in place: a private copy would live in scratch
+  lb_tile<D2Q9, T, TX, TY, 1>(sd.p, g + sd.g[par], g + sd.g[1 - par], phi + sd.phi[batch_phi_buf(sd, par)],
                               u + sd.u, tr.x0, tr.y0, 0);
 }
 
-// Substep s of every simulation with m > s.  The substep tile table lists
-// the simulations in decreasing m, so the launch of substep s covers a
-// prefix of it and every block has work.
+// Substep j of every simulation with m > j (one substep per launch).  The
+// substep tile table lists the simulations in decreasing m, so the launch
+// covers a prefix of it and every block has work.  Launch j reads phi from
+// buffer (start ^ jpar) and writes the other; jpar = j & 1 in a step (a
+// timing run passes 0: it then reads the state and writes the spare buffer).
 template <typename T, int TX, int TY, bool LAP5>
 __global__ void __launch_bounds__(NT) k_ch_batch(const SimDesc *__restrict__ sims, const TileRef *__restrict__ tiles,
-                                                 T *__restrict__ phi, const T *__restrict__ u, int par, int s) {
+                                                 T *__restrict__ phi, const T *__restrict__ u, int par, int j,
+                                                 int jpar, int, int) {
   int b, unused1, unused2;
   tile_coords(b, unused1, unused2);
   const TileRef tr = tiles[b];
-  const SimDesc sd = sims[tr.sim];
-  const int src = (batch_phi_buf(par, sd.m) + s) & 1;
+  const SimDesc &sd = sims[tr.sim];
+  const int src = batch_phi_buf(sd, par) ^ jpar;
   ch_tile<D2Q9, T, TX, TY, 1, LAP5>(sd.p, phi + sd.phi[src], u + sd.u, phi + sd.phi[1 - src], tr.x0, tr.y0, 0);
+}
+
+// Substeps jM .. min((j+1)M, m) - 1 of every simulation with m > jM in one
+// launch, on TO x TO tiles (2D): phi and u* are staged once with a halo of
+// 3M and each substep works on a region that shrinks by 3 on every side
+// (advection 1 + the two Laplacians of Eq. diff), entirely in LDS, as one
+// substep does: h with a halo of 2, the diffusion potential with a halo of
+// 1, then phi^{s+1} written over phi^s.  A simulation whose last launch has
+// fewer than M substeps left stops early (its output region is then wider
+// than needed).  Per launch phi and u* are read once and phi' written once.
+template <typename T, int M, int TO, bool LAP5>
+__global__ void __launch_bounds__(NT) k_chf_batch(const SimDesc *__restrict__ sims, const TileRef *__restrict__ tiles,
+                                                  T *__restrict__ phi, const T *__restrict__ u, int par, int j,
+                                                  int jpar, int, int) {
+  constexpr int H = 3 * M;
+  constexpr int L0 = TO + 2 * H;  // staged region edge
+  __shared__ T sphi[1][L0][L0], sux[1][L0][L0], suy[1][L0][L0];
+  __shared__ T sh[1][L0 - 2][L0 - 2], smu[1][L0 - 4][L0 - 4];
+  int b, unused1, unused2;
+  tile_coords(b, unused1, unused2);
+  const TileRef tr = tiles[b];
+  const SimDesc &sd = sims[tr.sim];
+  const KParams &p = sd.p;
+  const int src = batch_phi_buf(sd, par) ^ jpar;
+  const T *__restrict__ phi_in = phi + sd.phi[src];
+  T *__restrict__ phi_out = phi + sd.phi[1 - src];
+  const T *__restrict__ us = u + sd.u;
+  const int nsub = min(M, sd.m - j * M);
+  const int x0 = tr.x0, y0 = tr.y0;
+  const size_t ns = (size_t)p.ns;
+  {
+    TileLoad<2, T, L0, L0, 1> lphi, lux, luy;
+    lphi.issue(phi_in, p, x0 - H, y0 - H, 0);
+    lux.issue(us, p, x0 - H, y0 - H, 0);
+    luy.issue(us + ns, p, x0 - H, y0 - H, 0);
+    lphi.commit(sphi);
+    lux.commit(sux);
+    luy.commit(suy);
+  }
+  __syncthreads();
+  const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
+  const T a = T(p.a), bb = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cR = T(p.cR), cC = T(p.cC);
+  const bool flux = p.advection == 1;
+
+  for (int s = 0; s < nsub; s++) {
+    // input region of substep s: [3s, L0 - 3s) on both axes of the staged box
+    const int lo = 3 * s;
+    const int LH = L0 - 6 * s - 2;  // h region edge, origin lo + 1
+    for (int i = threadIdx.x; i < LH * LH; i += NT) {
+      const int y = lo + 1 + i / LH, x = lo + 1 + i % LH;
+      const T pc = sphi[0][y][x];
+      const T pw = sphi[0][y][x - 1], pe = sphi[0][y][x + 1];
+      const T pdn = sphi[0][y - 1][x], pup = sphi[0][y + 1][x];
+      const T uxc = sux[0][y][x], uxw = sux[0][y][x - 1], uxe = sux[0][y][x + 1];
+      const T uyc = suy[0][y][x], uyd = suy[0][y - 1][x], uyu = suy[0][y + 1][x];
+      T rhs;
+      if (!flux) {
+        const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
+        const T ty = pc * ((uyu - uyd) * T(0.5)) + uyc * (uyc > T(0) ? pc - pdn : pup - pc);
+        rhs = tx + ty;
+      } else {
+        const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
+        const T vyu = (uyc + uyu) * T(0.5), vyd = (uyd + uyc) * T(0.5);
+        const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
+        const T ty = (vyu > T(0) ? vyu * pc : vyu * pup) - (vyd > T(0) ? vyd * pdn : vyd * pc);
+        rhs = tx + ty;
+      }
+      sh[0][y - 1][x - 1] = pc - dt * rhs;
+    }
+    __syncthreads();
+    const int LM = LH - 2;  // potential region edge, origin lo + 2
+    for (int i = threadIdx.x; i < LM * LM; i += NT) {
+      const int y = lo + 2 + i / LM, x = lo + 2 + i % LM;
+      const int hy = y - 1, hx = x - 1;
+      const T hc = sh[0][hy][hx];
+      const T Lh = LAP5 ? lap5_at<2>(sh, hx, hy, 0, cQ, cC) : lap_at<2>(sh, hx, hy, 0, cQ, cR, cC);
+      const T ph = sphi[0][y][x];
+      smu[0][y - 2][x - 2] = a * hc + bb * ph * ph * ph - kappa * Lh;
+    }
+    __syncthreads();
+    const int LO = LM - 2;  // output region edge, origin lo + 3
+    for (int i = threadIdx.x; i < LO * LO; i += NT) {
+      const int y = lo + 3 + i / LO, x = lo + 3 + i % LO;
+      const int my = y - 2, mx = x - 2;
+      const T Lm = LAP5 ? lap5_at<2>(smu, mx, my, 0, cQ, cC) : lap_at<2>(smu, mx, my, 0, cQ, cR, cC);
+      sphi[0][y][x] = sh[0][y - 1][x - 1] + dtg * Lm;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < TO * TO; i += NT) {
+    const int ty = i / TO, tx = i % TO;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x < p.nx && y < p.ny) phi_out[x + p.nx * y] = sphi[0][H + ty][H + tx];
+  }
 }
 
 // M convection-diffusion substeps in one pass (2D, standard 5-point
@@ -570,20 +669,25 @@ __global__ void __launch_bounds__(NT) k_ch_batch(const SimDesc *__restrict__ sim
 // One barrier per row.  Output columns: the middle BW - 6M; output rows: the
 // segment [y0, y1) of the block.  phi and u* are read once and phi' written
 // once per site for all M substeps.
+// The block's output columns are [X0, X0 + ncol) (ncol <= BW - 6M) and its
+// output rows [y0, y1).
+template <typename T, int M, int BW>
+struct MarchLds {
+  T xphi[2][M][BW], xh[2][M][BW], xmu[2][M][BW];
+  T sux[4 * M][BW], suy[4 * M][BW];
+};
+
 template <typename T, int M, int BW, bool FLUX>
-__global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__restrict__ phi_in,
-                                                 const T *__restrict__ u, T *__restrict__ phi_out) {
+__device__ __forceinline__ void ch_march_body(MarchLds<T, M, BW> &lds, const KParams &p, int X0, int ncol, int y0,
+                                              int y1, const T *__restrict__ phi_in, const T *__restrict__ u,
+                                              T *__restrict__ phi_out) {
   constexpr int R = 4 * M;  // rows of the u* ring
-  __shared__ T xphi[2][M][BW], xh[2][M][BW], xmu[2][M][BW];
-  __shared__ T sux[R][BW], suy[R][BW];
+  auto &xphi = lds.xphi, &xh = lds.xh, &xmu = lds.xmu;
+  auto &sux = lds.sux, &suy = lds.suy;
   const int nx = p.nx, ny = p.ny;
   const int c = threadIdx.x;
-  int bx, by, bz;
-  tile_coords(bx, by, bz);
-  const int X0 = bx * (BW - 6 * M);
-  const int y0 = by * seg, y1 = min(y0 + seg, ny);
   const int gx = wrapc(X0 - 3 * M + c, nx);
-  const bool col_out = c >= 3 * M && c < BW - 3 * M && X0 + c - 3 * M < nx;
+  const bool col_out = c >= 3 * M && c < 3 * M + ncol && X0 + c - 3 * M < nx;
   const int cm = c > 0 ? c - 1 : 0, cp = c < BW - 1 ? c + 1 : BW - 1;  // edge lanes: values unused
   const size_t ns = (size_t)p.ns;
   const T *ux_g = u, *uy_g = u + ns;
@@ -686,6 +790,41 @@ __global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__
     iterate(t, 0);
     if (t + 1 < t1) iterate(t + 1, 1);
   }
+}
+
+template <typename T, int M, int BW, bool FLUX>
+__global__ void __launch_bounds__(BW) k_ch_march(KParams p, int seg, const T *__restrict__ phi_in,
+                                                 const T *__restrict__ u, T *__restrict__ phi_out) {
+  __shared__ MarchLds<T, M, BW> lds;
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int y0 = by * seg;
+  ch_march_body<T, M, BW, FLUX>(lds, p, bx * (BW - 6 * M), BW - 6 * M, y0, min(y0 + seg, p.ny), phi_in, u,
+                                phi_out);
+}
+
+// M substeps (one march) of the simulations of a group of a batch's substep
+// launch: a tile is (simulation, X0, y0) with output columns [X0, X0 + ncol)
+// and rows [y0, y0 + seg).  The tile table of a plan is blocked for the
+// plan's largest fuse, so a group that fuses fewer substeps (the last ones
+// of a simulation) uses the same table with M < fuse.
+template <typename T, int M, int BW>
+__global__ void __launch_bounds__(BW) k_chm_batch(const SimDesc *__restrict__ sims, const TileRef *__restrict__ tiles,
+                                                  T *__restrict__ phi, const T *__restrict__ u, int par, int j,
+                                                  int jpar, int seg, int ncol) {
+  __shared__ MarchLds<T, M, BW> lds;  // one allocation for both advection forms
+  int b, unused1, unused2;
+  tile_coords(b, unused1, unused2);
+  const TileRef tr = tiles[b];
+  const SimDesc &sd = sims[tr.sim];
+  const int src = batch_phi_buf(sd, par) ^ jpar;
+  const int y1 = min(tr.y0 + seg, sd.p.ny);
+  const T *in = phi + sd.phi[src];
+  T *out = phi + sd.phi[1 - src];
+  if (sd.p.advection == 1)
+    ch_march_body<T, M, BW, true>(lds, sd.p, tr.x0, ncol, tr.y0, y1, in, u + sd.u, out);
+  else
+    ch_march_body<T, M, BW, false>(lds, sd.p, tr.x0, ncol, tr.y0, y1, in, u + sd.u, out);
 }
 
 // M convection-diffusion substeps of one TO x TO tile in a single launch

@@ -402,8 +402,8 @@ class Batch:
 
     @property
     def plan(self):
-        """Tile shapes (lb_x, lb_y, substep_x, substep_y)."""
-        pl = (ctypes.c_int * 4)()
+        """(lb_x, lb_y, substep kind, substeps per launch, substep x, substep y)."""
+        pl = (ctypes.c_int * 6)()
         _bcheck(self.lib.hlb_batch_get_plan(self.b, pl), self.b)
         return tuple(pl)
 

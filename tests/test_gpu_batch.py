@@ -48,7 +48,7 @@ CASES = [
     ((40, 80), dict(BASE, N=1 / 3, Q=2 / 3, force_form=0), "spinodal"),
     ((33, 17), dict(BASE, N=0.5, Q=1.0, advection=1, cd_Q=2 / 3), "spinodal"),
     ((100, 96), dict(PAPER, tau=0.7, N=0.3, Q=2.5), "drop"),
-    ((8, 8), dict(BASE, m=2, g_ext=(1e-4, -2e-4)), "spinodal"),
+    ((8, 8), dict(BASE, kappa=0.05, m=4, g_ext=(1e-4, -2e-4)), "spinodal"),
     ((24, 72), dict(BASE, kappa=0.05, tau=1.4), "slab"),
     ((5, 3), dict(BASE, tau=0.8, kappa=0.2), "spinodal"),
     ((70, 37), dict(BASE, tau=0.6, kappa=0.16, N=1 / 3, Q=2 / 3), "drop"),
@@ -101,9 +101,13 @@ def test_batch_matches_oracle(hlb, storage, steps, lap5):
         print(f"sim {i} shape {shape} m {ms[i]} {kind}: {d}", flush=True)
         for k in d:
             assert d[k] < tol[k], (i, d)
-        st = batch.reduce(i)
+        # the reductions of the same state (the paper's advection form does
+        # not conserve total phi exactly, so it is compared, not pinned)
+        st, ro = batch.reduce(i), o.reduce()
         assert st["step"] == steps
-        assert abs(st["phi_sum"] - phi.sum()) < 1e-9 * phi.size
+        for k in ("mass", "phi_sum"):
+            assert abs(st[k] - ro[k]) < tol["phi"] * phi.size, (i, k, st[k], ro[k])
+        assert abs(st["umax"] - ro["umax"]) < tol["u"], i
     batch.close()
 
 
@@ -132,15 +136,31 @@ def test_batch_step_splits_agree(hlb):
                 assert np.array_equal(a[k], b[k])
 
 
-def test_batch_plans_agree(hlb):
-    """Every tile shape of both launches gives the same result as the
-    oracle; autotune keeps the state."""
-    cases = CASES
+NCH = 12  # substep plans: 0-3 tiles, 4 fused tiles, 5-11 marches (cd_Q = 1 only)
+MARCH0 = 5
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("lap5", [False, True], ids=["cdQ-mixed", "cdQ-1"])
+def test_batch_plans_agree(hlb, storage, lap5):
+    """Every tile shape of both launches, every fused substep plan and (when
+    every simulation has cd_Q = 1) every march gives the oracle's result;
+    autotune keeps the state."""
+    cases = _cases_without_lap_edge(CASES) if lap5 else CASES
     phis = [_phi(s, p, k, 30 + i) for i, (s, p, k) in enumerate(cases)]
     ref = [None] * len(cases)
+    tol = 1e-12 if storage == "f64" else 2e-6
     # the shapes of one class against the default shape of the other
-    for lb, ch in [(lb, 0) for lb in range(4)] + [(0, ch) for ch in range(1, 4)]:
-        batch = hlb.Batch([c[0] for c in cases], [c[1] for c in cases], "f64")
+    plans = [(lb, 0) for lb in range(4)] + [(0, ch) for ch in range(1, NCH if lap5 else MARCH0)]
+    if not lap5:
+        batch = hlb.Batch([c[0] for c in cases], [c[1] for c in cases], storage)
+        for ch in range(MARCH0, NCH):
+            with pytest.raises(hlb.HlbError) as e:
+                batch.set_plan(0, ch)
+            assert e.value.status == hlb.HLB_EINVAL
+        batch.close()
+    for lb, ch in plans:
+        batch = hlb.Batch([c[0] for c in cases], [c[1] for c in cases], storage)
         batch.set_plan(lb, ch)
         for i, phi in enumerate(phis):
             batch.init(i, phi)
@@ -149,10 +169,10 @@ def test_batch_plans_agree(hlb):
             if ref[i] is None:
                 ref[i] = _oracle(shape, p, phis[i], 20, batch.m[i]).fields()
             g = batch.fields(i)
-            assert np.abs(g["phi"] - ref[i]["phi"]).max() < 1e-12, (lb, ch, i)
-            assert np.abs(g["u"] - ref[i]["u"]).max() < 1e-13, (lb, ch, i)
+            assert np.abs(g["phi"] - ref[i]["phi"]).max() < tol, (lb, ch, batch.plan, i)
+            assert np.abs(g["u"] - ref[i]["u"]).max() < tol, (lb, ch, batch.plan, i)
         batch.close()
-    batch = hlb.Batch([c[0] for c in cases], [c[1] for c in cases], "f64")
+    batch = hlb.Batch([c[0] for c in cases], [c[1] for c in cases], storage)
     for i, phi in enumerate(phis):
         batch.init(i, phi)
     batch.step(9)
@@ -164,7 +184,29 @@ def test_batch_plans_agree(hlb):
         assert np.array_equal(a["phi"], b["phi"]) and np.array_equal(a["u"], b["u"])
     batch.step(11)
     for i, (shape, p, kind) in enumerate(cases):
-        assert np.abs(batch.fields(i)["phi"] - ref[i]["phi"]).max() < 1e-12, i
+        assert np.abs(batch.fields(i)["phi"] - ref[i]["phi"]).max() < tol, i
+    batch.close()
+
+
+def test_batch_plan_change_mid_run(hlb):
+    """Changing the substep plan between steps, after odd and even step
+    counts, keeps every simulation's phi where the next step reads it (the
+    number of launches per step, and so the buffer parity, changes with the
+    plan)."""
+    cases = _cases_without_lap_edge(CASES)
+    phis = [_phi(s, p, k, 50 + i) for i, (s, p, k) in enumerate(cases)]
+    batch = hlb.Batch([c[0] for c in cases], [c[1] for c in cases], "f64")
+    for i, phi in enumerate(phis):
+        batch.init(i, phi)
+    total = 0
+    for plan, steps in (((0, 0), 3), ((1, 5), 4), ((0, 4), 1), ((2, 11), 3), ((0, 8), 2), ((3, 1), 1),
+                        ((0, 6), 3), ((1, 9), 2)):
+        batch.set_plan(*plan)
+        batch.step(steps)
+        total += steps
+    for i, (shape, p, kind) in enumerate(cases):
+        o = _oracle(shape, p, phis[i], total, batch.m[i])
+        assert np.abs(batch.fields(i)["phi"] - o.fields()["phi"]).max() < 1e-12, i
     batch.close()
 
 
@@ -184,11 +226,15 @@ def test_batch_init_mid_run_and_errors(hlb):
     assert np.abs(batch.fields(1)["phi"] - o.fields()["phi"]).max() < 1e-12
     o0 = _oracle(cases[0][0], cases[0][1], phis[0], 11, batch.m[0])
     assert np.abs(batch.fields(0)["phi"] - o0.fields()["phi"]).max() < 1e-12
-    with pytest.raises(hlb.HlbError) as e:
-        batch.fields(3)
-    assert e.value.status == hlb.HLB_EINVAL
+    lib = hlb.load()
+    for bad in (3, -1):
+        assert lib.hlb_batch_get_fields(batch.b, bad, None, None, None, None) == hlb.HLB_EINVAL
+        assert lib.hlb_batch_init_fields(batch.b, bad, None, None, None) == hlb.HLB_EINVAL
+    assert b"simulation index" in lib.hlb_batch_last_error(batch.b)
     with pytest.raises(hlb.HlbError):
         batch.set_plan(4, 0)
+    with pytest.raises(hlb.HlbError):
+        batch.set_plan(0, NCH)
     with pytest.raises(hlb.HlbError):
         batch.step(-1)
     batch.close()
@@ -199,8 +245,8 @@ def test_batch_full_size_sampled(hlb):
     {64..256}, kappa ~ U(0.05, 0.2), tau ~ U(0.6, 1.5), drops and slabs,
     FP32), built and autotuned as the benchmark does: after 20 steps
     three sampled simulations (the smallest, the largest and the one with
-    the most substeps) agree with the oracle, and every simulation conserves
-    total phi and mass (Sec. 2: both are conserved by the scheme)."""
+    the most substeps) agree with the oracle, and every simulation keeps its
+    total mass (the collision conserves it) and a low-Mach velocity field."""
     import bench
 
     specs, params, phis = bench.batch_workload()
@@ -221,6 +267,6 @@ def test_batch_full_size_sampled(hlb):
     for i in range(len(specs)):
         st = batch.reduce(i)
         ns = phis[i].size
-        assert abs(st["phi_sum"] - phis[i].sum()) < 2e-5 * ns, i
+        assert st["finite"] and st["umax"] < 0.05, i
         assert abs(st["mass"] - ns) < 2e-5 * ns, i
     batch.close()
