@@ -198,6 +198,7 @@ def run_gpu_batch(name, steps, warmup, plan=None):
     ms_lb, ms_ch = batch.step_timed(nprof)
     stats = [batch.reduce(i, raise_on_error=False) for i in range(len(shapes))]
     tile_plan = batch.plan
+    plan_index = batch.plan_index
     batch.close()
     kind, fuse = tile_plan[2], tile_plan[3]
     lb_b, ch_b, step_b = algorithmic_bytes(2, 9, es)
@@ -225,7 +226,7 @@ def run_gpu_batch(name, steps, warmup, plan=None):
         "stats": {"finite": all(s["finite"] for s in stats), "mass": sum(s["mass"] for s in stats),
                   "umax": max(s["umax"] for s in stats),
                   "umax_sim": max(range(len(stats)), key=lambda i: stats[i]["umax"])},
-        "plan": tile_plan,
+        "plan": tile_plan, "plan_index": plan_index,
         "kernels": {"lb": {"name": lbname, "us_per_launch": t_lb * 1e6, "bytes_per_lu": lb_b, "gbs": lb_gbs},
                     "ch": {"name": chname, "us_per_launch": t_ch * 1e6, "launches_per_step": nlaunch,
                            "substeps_per_launch": fuse, "substep_site_updates_per_step": sub_sites,
@@ -313,7 +314,8 @@ def main():
     ap.add_argument("--workload", default="d2q9_spinodal_1024", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default=None,
-                    help="substep plan kind,fuse,bw,seg to use instead of autotuning (e.g. for profiler runs)")
+                    help="plan to use instead of autotuning (e.g. for profiler runs): kind,fuse,bw,seg for one "
+                         "simulation, lb,substep candidate indices for a batch")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a device copy of this many MiB (for the HBM counter scale)")
     args = ap.parse_args()
@@ -359,7 +361,8 @@ def main():
         "dtype": "f32" if r["storage"] == "f32" else "f64",
         "data": "synthetic",
         "config": ({"workload": r["desc"], "lattice": "D2Q9", "nsim": r["nsim"], "sites": r["sites"],
-                    "m": r["m"], "tile_plan": list(r["plan"]), "stencil": "N=0.3, Q=2.5",
+                    "m": r["m"], "tile_plan": list(r["plan"]), "substep_plan": list(r["plan_index"]),
+                    "stencil": "N=0.3, Q=2.5",
                     "params": "a=-0.1 b=0.1 Gamma=1, kappa and tau per simulation", "seed": 0}
                    if batched else
                    {"workload": r["desc"], "lattice": "D2Q9" if r["d"] == 2 else "D3Q19",

@@ -206,6 +206,25 @@ hlb_status hlb_autotune(hlb_ctx *ctx, double *best_us);
  * lattice, storage and plan, as they appear in profiler traces. */
 const char *hlb_kernel_name(const hlb_ctx *ctx, int kernel_class);
 
+/* Checkpoints.  A timestep depends only on (f_t, phi_t) and the parameters
+ * (Sec. 2: the force, u*, the collision and the substeps are all computed
+ * from the state at time t), so a checkpoint holds a header (lattice,
+ * storage, size, step counter, hlb_params) and the state in its device
+ * representation (populations as stored, then phi), and a resumed run is
+ * bit-identical to an uninterrupted one.
+ *
+ * hlb_checkpoint_size: bytes of a checkpoint of this context.
+ * hlb_save: writes the checkpoint into the caller's host buffer (at least
+ *   hlb_checkpoint_size bytes; HLB_EINVAL otherwise).  HLB_ESTATE after a
+ *   non-finite state.  Synchronises.
+ * hlb_load: restores a checkpoint of a context with the same lattice,
+ *   storage and size (HLB_ESHAPE otherwise; HLB_EINVAL for a buffer that is
+ *   not a checkpoint or is truncated), including the step counter and the
+ *   parameters, and clears the error state.  Synchronises. */
+hlb_status hlb_checkpoint_size(const hlb_ctx *ctx, size_t *bytes);
+hlb_status hlb_save(hlb_ctx *ctx, void *host, size_t bytes);
+hlb_status hlb_load(hlb_ctx *ctx, const void *host, size_t bytes);
+
 /* Message of the context's last failure ("" if none); owned by the context,
  * valid until its next call.  ctx may be NULL for failures of hlb_create. */
 const char *hlb_last_error(const hlb_ctx *ctx);
@@ -290,10 +309,11 @@ hlb_status hlb_batch_step_timed(hlb_batch *b, long long nsteps, double ms[2]);
  * tables and synchronises. */
 hlb_status hlb_batch_set_plan(hlb_batch *b, const int plan[2]);
 
-/* The current plan as plan = {lb_x, lb_y, substep kind (0 tiles, 1 fused
- * tiles, 2 march), substeps per launch, substep x, substep y}; for a march,
- * x is the block's columns and y its rows per segment. */
-hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[6]);
+/* The current plan as plan = {lb index, substep index (the arguments of
+ * hlb_batch_set_plan), lb_x, lb_y, substep kind (0 tiles, 1 fused tiles,
+ * 2 march), substeps per launch, substep x, substep y}; for a march, x is
+ * the block's columns and y its rows per segment. */
+hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[8]);
 
 /* Times every candidate of both launch classes on the current state (the
  * timed launches write only buffers that are not state between steps, so

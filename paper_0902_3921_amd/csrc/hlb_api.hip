@@ -815,6 +815,87 @@ hlb_status hlb_get_state(hlb_ctx *c, double *f, double *phi) {
   return HLB_OK;
 }
 
+// ----------------------------------------------------------- checkpoints
+// A checkpoint holds a header and the device representation of the state
+// (populations as stored, then phi), so a resumed run is bit-identical to
+// an uninterrupted one: a timestep is a function of (f_t, phi_t) and the
+// parameters only, and no kernel depends on anything else.
+namespace {
+constexpr char kCkptMagic[8] = {'H', 'L', 'B', 'C', 'K', 'P', 'T', '1'};
+struct CkptHeader {
+  char magic[8];
+  int lattice, storage, nx, ny, nz, q;
+  long long step;
+  hlb_params p;
+};
+size_t ckpt_bytes(const hlb_ctx *c) {
+  const size_t es = c->storage == HLB_F64 ? 8 : 4;
+  return sizeof(CkptHeader) + (size_t)(c->q + 1) * (size_t)c->ns * es;
+}
+}  // namespace
+
+hlb_status hlb_checkpoint_size(const hlb_ctx *c, size_t *bytes) {
+  if (!c || !bytes) return HLB_EINVAL;
+  *bytes = ckpt_bytes(c);
+  return HLB_OK;
+}
+
+hlb_status hlb_save(hlb_ctx *c, void *host, size_t bytes) {
+  hlb_status s = usable(c);
+  if (s != HLB_OK) return s;
+  if (!host || bytes < ckpt_bytes(c)) return fail(c, HLB_EINVAL, "checkpoint buffer missing or too small");
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, sizeof h.magic);
+  h.lattice = c->lattice;
+  h.storage = c->storage;
+  h.nx = c->nx;
+  h.ny = c->ny;
+  h.nz = c->nz;
+  h.q = c->q;
+  h.step = c->step;
+  h.p = c->p;
+  char *dst = static_cast<char *>(host);
+  std::memcpy(dst, &h, sizeof h);
+  const size_t es = c->storage == HLB_F64 ? 8 : 4;
+  const size_t gbytes = (size_t)c->q * (size_t)c->ns * es, pbytes = (size_t)c->ns * es;
+  hipError_t e = hipMemcpyAsync(dst + sizeof h, c->ws + c->lay.g[c->gcur], gbytes, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(dst + sizeof h + gbytes, c->ws + c->lay.phi[c->phicur], pbytes, hipMemcpyDeviceToHost,
+                       c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  return sync(c);
+}
+
+hlb_status hlb_load(hlb_ctx *c, const void *host, size_t bytes) {
+  if (!c) return HLB_EINVAL;
+  if (!host || bytes < sizeof(CkptHeader)) return fail(c, HLB_EINVAL, "checkpoint missing or truncated");
+  CkptHeader h;
+  std::memcpy(&h, host, sizeof h);
+  if (std::memcmp(h.magic, kCkptMagic, sizeof h.magic) != 0) return fail(c, HLB_EINVAL, "not a checkpoint");
+  if (h.lattice != c->lattice || h.storage != c->storage || h.nx != c->nx || h.ny != c->ny || h.nz != c->nz ||
+      h.q != c->q)
+    return fail(c, HLB_ESHAPE, "checkpoint of another lattice, storage or size");
+  if (bytes < ckpt_bytes(c)) return fail(c, HLB_EINVAL, "checkpoint truncated");
+  std::string msg;
+  int m = 0;
+  hlb_status s = validate(c->lattice, &h.p, &m, &msg);
+  if (s != HLB_OK) return fail(c, s, "checkpoint parameters: " + msg);
+  const char *src = static_cast<const char *>(host);
+  const size_t es = c->storage == HLB_F64 ? 8 : 4;
+  const size_t gbytes = (size_t)c->q * (size_t)c->ns * es, pbytes = (size_t)c->ns * es;
+  hipError_t e = hipMemcpyAsync(c->ws + c->lay.g[0], src + sizeof h, gbytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->ws + c->lay.phi[0], src + sizeof h + gbytes, pbytes, hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  s = sync(c);
+  if (s != HLB_OK) return s;
+  c->gcur = 0;
+  c->phicur = 0;
+  c->step = h.step;
+  c->error_state = false;
+  return hlb_set_params(c, &h.p);
+}
+
 hlb_status hlb_step(hlb_ctx *c, long long nsteps) {
   hlb_status s = usable(c);
   if (s != HLB_OK) return s;
@@ -1692,15 +1773,17 @@ hlb_status hlb_batch_set_plan(hlb_batch *b, const int plan[2]) {
   return batch_tables(b, plan[0], plan[1]);
 }
 
-hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[6]) {
+hlb_status hlb_batch_get_plan(const hlb_batch *b, int plan[8]) {
   if (!b || !plan) return HLB_EINVAL;
   const ChShape c = ch_shape(b->storage, b->ch_plan);
-  plan[0] = kBatchLB[b->lb_plan].x;
-  plan[1] = kBatchLB[b->lb_plan].y;
-  plan[2] = c.kind;
-  plan[3] = c.fuse;
-  plan[4] = c.x;
-  plan[5] = c.y;
+  plan[0] = b->lb_plan;
+  plan[1] = b->ch_plan;
+  plan[2] = kBatchLB[b->lb_plan].x;
+  plan[3] = kBatchLB[b->lb_plan].y;
+  plan[4] = c.kind;
+  plan[5] = c.fuse;
+  plan[6] = c.x;
+  plan[7] = c.y;
   return HLB_OK;
 }
 

@@ -28,6 +28,7 @@ EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_
            "hlb_set_params", "hlb_get_params", "hlb_init_fields", "hlb_set_state", "hlb_get_state",
            "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name",
            "hlb_set_plan", "hlb_get_plan", "hlb_autotune", "hlb_last_error", "hlb_destroy", "hlb_version",
+           "hlb_checkpoint_size", "hlb_save", "hlb_load",
            "hlb_batch_workspace_size", "hlb_batch_create", "hlb_batch_info", "hlb_batch_init_fields",
            "hlb_batch_step", "hlb_batch_step_timed", "hlb_batch_set_plan", "hlb_batch_get_plan", "hlb_batch_autotune",
            "hlb_batch_get_fields", "hlb_batch_reduce", "hlb_batch_last_error",
@@ -96,6 +97,9 @@ def load():
         "hlb_last_error": (ctypes.c_char_p, [_vp]),
         "hlb_destroy": (st, [_vp]),
         "hlb_version": (ctypes.c_char_p, []),
+        "hlb_checkpoint_size": (st, [_vp, ctypes.POINTER(ctypes.c_size_t)]),
+        "hlb_save": (st, [_vp, _vp, ctypes.c_size_t]),
+        "hlb_load": (st, [_vp, _vp, ctypes.c_size_t]),
         "hlb_batch_workspace_size": (st, [ctypes.c_int, ctypes.c_int, _ip, _ip, ctypes.POINTER(ctypes.c_size_t)]),
         "hlb_batch_create": (st, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, _ip, _ip,
                                   ctypes.POINTER(Params), _vp, ctypes.c_size_t, _vp]),
@@ -263,6 +267,22 @@ class Sim:
         _check(self.lib.hlb_get_state(self.ctx, _ptr(f), _ptr(phi)), self.ctx)
         return f, phi
 
+    # -- checkpoints
+    def save(self) -> bytes:
+        """The state, step counter and parameters as a checkpoint blob."""
+        n = ctypes.c_size_t()
+        _check(self.lib.hlb_checkpoint_size(self.ctx, ctypes.byref(n)), self.ctx)
+        buf = ctypes.create_string_buffer(n.value)
+        _check(self.lib.hlb_save(self.ctx, buf, n.value), self.ctx)
+        return buf.raw
+
+    def load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        _check(self.lib.hlb_load(self.ctx, buf, len(blob)), self.ctx)
+        self._params = Params()
+        _check(self.lib.hlb_get_params(self.ctx, ctypes.byref(self._params), None), self.ctx)
+        return self
+
     # -- stepping
     def step(self, nsteps: int = 1):
         _check(self.lib.hlb_step(self.ctx, int(nsteps)), self.ctx)
@@ -403,7 +423,15 @@ class Batch:
     @property
     def plan(self):
         """(lb_x, lb_y, substep kind, substeps per launch, substep x, substep y)."""
-        pl = (ctypes.c_int * 6)()
+        return self._plan()[2:]
+
+    @property
+    def plan_index(self):
+        """The (lb, substep) candidate indices of set_plan."""
+        return self._plan()[:2]
+
+    def _plan(self):
+        pl = (ctypes.c_int * 8)()
         _bcheck(self.lib.hlb_batch_get_plan(self.b, pl), self.b)
         return tuple(pl)
 

@@ -8,6 +8,8 @@ by element.  Tolerances:
   * FP32 storage: max |dphi|, |du| <= 1e-5 after 1000 steps of the 128^2
     drop (the target stated for this workload); shorter runs in proportion.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -353,3 +355,40 @@ def test_d3q19_march_thin_lattices(hlb):
         ora.step(3)
         d = _maxdiff(gpu, ora)
         assert max(d.values()) < 1e-13, (shape, d)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_checkpoint_resume_bit_exact(hlb, storage):
+    """hlb_save / hlb_load: a run resumed from a checkpoint (into a context
+    created with other parameters, which the checkpoint's replace) is bit
+    for bit the uninterrupted run, and the step counter comes back."""
+    shape = (48, 80)
+    phi = _drop(shape, 12, BASE)
+    a = hlb.Sim(shape, storage, **BASE, N=0.3, Q=2.5)
+    a.init(phi)
+    a.step(7)
+    blob = a.save()
+    a.step(9)
+    fa, sa = a.fields(), a.state()
+    b = hlb.Sim(shape, storage, **dict(BASE, tau=0.7), N=0.5, Q=1.0)
+    b.load(blob)
+    assert b.reduce()["step"] == 7
+    assert abs(b._params.tau - 1.0) < 1e-15 and abs(b._params.N - 0.3) < 1e-15
+    b.step(9)
+    fb, sb = b.fields(), b.state()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(sa[0], sb[0]) and np.array_equal(sa[1], sb[1])
+    lib = hlb.load()
+    other = hlb.Sim((48, 81), storage, **BASE)
+    with pytest.raises(hlb.HlbError) as e:
+        other.load(blob)
+    assert e.value.status == hlb.HLB_ESHAPE
+    with pytest.raises(hlb.HlbError) as e:
+        b.load(b"not a checkpoint" * 8)
+    assert e.value.status == hlb.HLB_EINVAL
+    with pytest.raises(hlb.HlbError) as e:
+        b.load(blob[: len(blob) // 2])
+    assert e.value.status == hlb.HLB_EINVAL
+    buf = ctypes.create_string_buffer(16)
+    assert lib.hlb_save(b.ctx, buf, 16) == hlb.HLB_EINVAL
