@@ -10,9 +10,9 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhlb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = [os.path.join(CSRC, "hlb_api.hip")]
-HEADERS = [os.path.join(CSRC, h) for h in ("kernels.hpp", "lattice.hpp")] + [
-    os.path.join(ROOT, "include", "hlb.h")]
+SOURCES = [os.path.join(CSRC, "hlb_api.hip"), os.path.join(CSRC, "sur_api.hip")]
+HEADERS = [os.path.join(CSRC, h) for h in ("kernels.hpp", "lattice.hpp", "sur_kernels.hpp")] + [
+    os.path.join(ROOT, "include", h) for h in ("hlb.h", "sur.h")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

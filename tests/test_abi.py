@@ -22,17 +22,22 @@ def hlb():
 
 
 def _declared():
-    text = open(os.path.join(ROOT, "include", "hlb.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(hlb_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in ("hlb.h", "sur.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b((?:hlb|sur)_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol(hlb):
+    from paper_0902_3921_amd import sur
+
     declared = _declared()
-    assert set(declared) == set(hlb.EXPORTS)
+    assert set(declared) == set(hlb.EXPORTS) | set(sur.EXPORTS)
     out = subprocess.run(["nm", "-D", "--defined-only", hlb.LIB_PATH], capture_output=True, text=True,
                          check=True).stdout
-    exported = set(re.findall(r"\bT (hlb_[a-z_]+)$", out, flags=re.M))
+    exported = set(re.findall(r"\bT ((?:hlb|sur)_[a-z_]+)$", out, flags=re.M))
     assert set(declared) <= exported, set(declared) - exported
     for name in declared:
         assert getattr(hlb.load(), name)
@@ -134,3 +139,26 @@ def test_batch_create_rejects_before_touching_the_device(hlb):
     st = lib.hlb_batch_create(ctypes.byref(b), 1, 2, nx, ny, ps, None, 0, None)
     assert st == hlb.HLB_ESHAPE and not b.value
     assert b"workspace" in lib.hlb_batch_last_error(None)
+
+
+def test_surrogate_parameter_count_and_config_checks(hlb):
+    """The library's parameter layout has the oracle's size for several
+    widths, and invalid configurations are rejected on the host."""
+    from oracle import unet
+    from paper_0902_3921_amd import sur
+
+    for widths in ((32, 64, 128), (8, 16, 24), (5, 7, 3)):
+        c0, c1, c2 = widths
+        assert sur.param_count(c0=c0, c1=c1, c2=c2) == unet.param_count(c0, c1, c2)
+    lib = sur._lib()
+    n = ctypes.c_size_t()
+    for bad in (dict(height=30), dict(width=0), dict(batch=0), dict(c1=0)):
+        c = sur.config(**bad)
+        assert lib.sur_workspace_size(ctypes.byref(c), ctypes.byref(n)) == hlb.HLB_EINVAL
+    c = sur.config(batch=4, height=64, width=64)
+    assert lib.sur_workspace_size(ctypes.byref(c), ctypes.byref(n)) == hlb.HLB_OK
+    # activations and gradients at full resolution alone: 4 images x 64 x 64 x (3 + 3 + 32 + 96 + ...) floats
+    assert n.value > 4 * 64 * 64 * (2 * 3 + 2 * 32 + 2 * 96) * 4
+    net = ctypes.c_void_p()
+    assert lib.sur_create(ctypes.byref(net), ctypes.byref(c), None, 0, None) == hlb.HLB_ESHAPE
+    assert b"workspace" in lib.sur_last_error(None)

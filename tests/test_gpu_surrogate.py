@@ -1,0 +1,170 @@
+"""Parity of the surrogate network (include/sur.h) with its FP64 oracle
+(oracle/unet.py).
+
+Both sides round the convolution inputs and weights to bfloat16 at the same
+points; they differ in the accumulation (FP32 on the matrix cores, FP64 in
+the oracle).  An element whose exact value lies within the accumulation
+error of a bfloat16 rounding midpoint rounds the other way on one side (a
+2^-8 relative step), and eleven layers carry such steps to the output.  How
+large that is was measured by running the oracle itself with FP32
+accumulation (same rounding points, another summation order) against FP64,
+on the inputs of these tests: the residual increment y - x differs by
+1.0e-3, 3.6e-4 and 2.5e-3 relative L2 (32 x 32, 20 x 12, 64 x 48; largest
+element 5e-3 of the largest increment), and the gradient by 8.3e-3 relative
+L2 (worst layer block 1.8e-2, no sign change where |g| > 0.1 rms).  The
+bounds are about four times those figures:
+  * forward increment: relative L2 <= 1e-2, largest difference <= 3e-2 of
+    the largest increment;
+  * gradient: relative L2 <= 2.5e-2 overall and <= 6e-2 per layer block;
+  * Adam: where |g| > 0.1 rms the step equals the oracle's.
+A wrong tap, channel slice, bias or skip connection changes the output by
+O(1).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import unet
+
+pytestmark = pytest.mark.gpu
+
+SCALE = np.array([1.0, 0.01, 0.01])
+
+
+@pytest.fixture(scope="module")
+def sur():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_0902_3921_amd import sur as mod
+
+    mod._lib()
+    return mod
+
+
+def _state(batch, h, w, seed):
+    """Synthetic states: phi ~ U(-1, 1), rho u ~ U(-0.01, 0.01), NHWC."""
+    out = np.empty((batch, h, w, 3))
+    for b in range(batch):
+        out[b, ..., 0] = synth.spinodal((h, w), seed + 3 * b, 1.0)
+        out[b, ..., 1] = synth.spinodal((h, w), seed + 3 * b + 1, 0.01)
+        out[b, ..., 2] = synth.spinodal((h, w), seed + 3 * b + 2, 0.01)
+    return out
+
+
+def _dev(a):
+    import torch
+
+    return torch.tensor(np.asarray(a, dtype=np.float32), device="cuda").contiguous()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("batch,h,w", [(2, 32, 32), (3, 20, 12), (1, 64, 48)])
+def test_forward_matches_oracle(sur, batch, h, w):
+    """Tiles that are whole (32 x 32), ragged and smaller than a tile at the
+    coarse levels (20 x 12: 5 x 3 at quarter resolution)."""
+    params = sur.he_init(1, batch=batch, height=h, width=w)
+    net = sur.Surrogate(batch=batch, height=h, width=w)
+    net.set_params(params)
+    x = _state(batch, h, w, 10)
+    y = net.forward(_dev(x)).cpu().numpy().astype(np.float64)
+    yo, _ = unet.forward(params, x / SCALE)
+    yo = yo.numpy() * SCALE
+    inc, inc_o = y - x, yo - x
+    rel = _rel(inc, inc_o)
+    mx = np.abs(inc - inc_o).max() / np.abs(inc_o).max()
+    print(f"forward {batch}x{h}x{w}: increment rel L2 {rel:.2e}, max {mx:.2e}", flush=True)
+    assert rel <= 1e-2 and mx <= 3e-2
+
+
+def test_loss_and_gradients_match_oracle(sur):
+    batch, h, w = 2, 32, 32
+    params = sur.he_init(2, batch=batch, height=h, width=w)
+    net = sur.Surrogate(batch=batch, height=h, width=w)
+    net.set_params(params)
+    x = _state(batch, h, w, 20)
+    t = _state(batch, h, w, 30)
+    loss, g = net.loss_grad(_dev(x), _dev(t), grads=True)
+    lo, go, _ = unet.loss_and_grads(params, x / SCALE, t / SCALE)
+    rel = _rel(g.astype(np.float64), go)
+    print(f"loss {loss:.6e} oracle {lo:.6e}; gradient rel L2 {rel:.2e}", flush=True)
+    assert abs(loss / lo - 1) < 1e-4
+    assert rel <= 2.5e-2
+    # every layer's weight and bias block, not only the total
+    off = 0
+    for name, ci, co, taps, _ in unet.layers():
+        for n in (taps * ci * co, co):
+            blk = slice(off, off + n)
+            assert _rel(g[blk].astype(np.float64), go[blk]) <= 6e-2, (name, n)
+            off += n
+
+
+def test_adam_step_matches_oracle(sur):
+    """One Adam step: each parameter moves by lr g / (|g| + eps), so where
+    the gradient is well above the gradient noise the GPU step equals the
+    oracle's, and nowhere does it exceed lr."""
+    batch, h, w = 1, 32, 32
+    params = sur.he_init(3, batch=batch, height=h, width=w)
+    net = sur.Surrogate(batch=batch, height=h, width=w)
+    net.set_params(params)
+    x = _state(batch, h, w, 40)
+    t = _state(batch, h, w, 41)
+    net.loss_grad(_dev(x), _dev(t))
+    lr = 1e-3
+    net.adam_step(lr)
+    p1 = net.params().astype(np.float64)
+    _, go, _ = unet.loss_and_grads(params, x / SCALE, t / SCALE)
+    po, _, _ = unet.adam(params, go, np.zeros_like(go), np.zeros_like(go), 1, lr)
+    big = np.abs(go) > 0.1 * np.sqrt(np.mean(go ** 2))
+    assert big.mean() > 0.3
+    assert np.abs(p1 - po)[big].max() < 1e-3 * lr + 1e-7
+    assert np.abs(p1 - params).max() <= lr * (1 + 1e-3) + 1e-7
+
+
+def test_training_steps_reduce_the_loss(sur):
+    """A property that holds for any correct gradient: a few small Adam
+    steps on one batch lower its loss."""
+    batch, h, w = 2, 32, 32
+    net = sur.Surrogate(batch=batch, height=h, width=w)
+    net.set_params(sur.he_init(4, batch=batch, height=h, width=w))
+    x, t = _dev(_state(batch, h, w, 50)), _dev(_state(batch, h, w, 50) * 0.9)
+    l0 = net.loss_grad(x, t)
+    for _ in range(20):
+        net.adam_step(1e-3)
+        net.loss_grad_async(x, t)
+    l1 = net.loss_grad(x, t)
+    print(f"loss {l0:.4e} -> {l1:.4e}", flush=True)
+    assert l1 < 0.7 * l0
+
+
+def test_full_size_forward_matches_oracle(sur):
+    """The benchmark's configuration: one 256 x 256 state."""
+    params = sur.he_init(5)
+    net = sur.Surrogate()
+    net.set_params(params)
+    x = _state(1, 256, 256, 60)
+    y = net.forward(_dev(x)).cpu().numpy().astype(np.float64)
+    yo, _ = unet.forward(params, x / SCALE)
+    yo = yo.numpy() * SCALE
+    rel = _rel(y - x, yo - x)
+    print(f"forward 256x256: increment rel L2 {rel:.2e}", flush=True)
+    assert rel <= 1e-2
+
+
+def test_invalid_calls(sur):
+    import torch
+
+    net = sur.Surrogate(batch=2, height=16, width=16)
+    x = torch.zeros((3, 16, 16, 3), device="cuda")
+    from paper_0902_3921_amd import hlb
+
+    with pytest.raises(hlb.HlbError) as e:
+        net.forward(x)
+    assert e.value.status == hlb.HLB_EINVAL
+    with pytest.raises(hlb.HlbError) as e:
+        net.adam_step(1e-3)
+    assert e.value.status == hlb.HLB_ESTATE
