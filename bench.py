@@ -236,6 +236,64 @@ def run_gpu_batch(name, steps, warmup, plan=None):
     }
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16
+
+
+def run_surrogate(args):
+    """The surrogate workload: a 100-jump rollout (50 steps a jump) of a
+    held-out 256 x 256 spinodal trajectory from t = 1000, checked against the
+    GPU solver every 10 jumps with fallback above 1e-2 relative L2 phi error;
+    value = solver time / rollout time.  Roofline: the convolution kernels of
+    one forward against the bf16 matrix-core peak."""
+    import numpy as np
+    import torch
+
+    from paper_0902_3921_amd import sur, surrogate_train as st
+
+    params = st.load()
+    net = sur.Surrogate(batch=1)
+    net.set_params(params)
+    r = st.rollout(net, seed=100001, jumps=100, check_every=10, tol=1e-2, log=lambda *a, **k: None)
+    x = torch.from_numpy(np.zeros((1, st.SIZE, st.SIZE, 3), np.float32)).cuda()
+    x[..., 0] = torch.rand((st.SIZE, st.SIZE), device="cuda") * 2 - 1
+    y = torch.empty_like(x)
+    net.forward_timed(x, y, reps=3)
+    ms_conv, ms_total, flops = net.forward_timed(x, y, reps=50)
+    achieved = flops / (ms_conv * 1e-3) / 1e12
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import unet
+
+        xs = np.random.default_rng(0).uniform(-1, 1, (1, st.SIZE, st.SIZE, 3))
+        unet.forward(params, xs)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < 15.0:
+            unet.forward(params, xs)
+            n += 1
+        secs = time.perf_counter() - t0
+        cpu = {"value": n / secs, "unit": "jumps/s", "cores": torch.get_num_threads(), "kind": "oracle",
+               "sample": f"{n} FP64 oracle forwards of one 256x256 state (one jump each)"}
+    speedup = r["solver_s"] / r["rollout_s"]
+    out = {
+        "metric": "surrogate speedup at <=1e-2 phi err (rollout vs plain GPU solver)",
+        "value": speedup, "unit": "x", "n_gpus": 1, "steps": r["jumps"], "warmup": 1,
+        "ms_per_step": r["rollout_s"] / r["jumps"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "surrogate U-Net, 256x256 D2Q9 spinodal, 100 jumps of 50 steps from t=1000, "
+                               "checked every 10 jumps, fallback above 1e-2 relative L2 phi error",
+                   "params": int(params.size), "seed": 100001},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / MFMA_BF16_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "sur::k_conv (all convolutions of one forward)", "flops_per_launch": flops},
+        "rollout": {"solver_ms": r["solver_s"] * 1e3, "rollout_ms": r["rollout_s"] * 1e3,
+                    "fallbacks": r["fallbacks"], "phi_rel_l2_at_checks": r["errors"],
+                    "forward_ms": ms_total, "conv_ms": ms_conv},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def measured_traffic(name, kernel_name):
     """HBM bytes per launch of a kernel from the committed rocprofv3 summary of
     this workload (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the
@@ -311,7 +369,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="d2q9_spinodal_1024", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="d2q9_spinodal_1024", choices=sorted(WORKLOADS) + ["surrogate_256"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plan", default=None,
                     help="plan to use instead of autotuning (e.g. for profiler runs): kind,fuse,bw,seg for one "
@@ -331,6 +389,9 @@ def main():
         sys.exit(1)
     torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
 
+    if args.workload == "surrogate_256":
+        run_surrogate(args)
+        return
     plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
     batched = WORKLOADS[args.workload][0] is None
     r = (run_gpu_batch if batched else run_gpu)(args.workload, args.steps, args.warmup, plan)

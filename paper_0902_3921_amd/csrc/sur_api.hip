@@ -430,7 +430,7 @@ hlb_status sur_config_default(sur_config *c) {
   c->c1 = 64;
   c->c2 = 128;
   c->scale[0] = 1.0;
-  c->scale[1] = c->scale[2] = 0.01;
+  c->scale[1] = c->scale[2] = 0.05;
   return HLB_OK;
 }
 

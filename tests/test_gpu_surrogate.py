@@ -28,7 +28,7 @@ from oracle import unet
 
 pytestmark = pytest.mark.gpu
 
-SCALE = np.array([1.0, 0.01, 0.01])
+SCALE = np.array([1.0, 0.05, 0.05])  # the library's default normalisation
 
 
 @pytest.fixture(scope="module")
@@ -168,3 +168,21 @@ def test_invalid_calls(sur):
     with pytest.raises(hlb.HlbError) as e:
         net.adam_step(1e-3)
     assert e.value.status == hlb.HLB_ESTATE
+
+
+def test_rollout_checks_and_falls_back(sur):
+    """The rollout compares phi with the solver at every check and replaces
+    a state whose error is above the tolerance by the solver's: with an
+    untrained network every check fails and the next segment starts from
+    the solver (its error is that of one segment, not accumulated); with an
+    infinite tolerance nothing is replaced."""
+    from paper_0902_3921_amd import surrogate_train as st
+
+    net = sur.Surrogate(batch=1)
+    net.set_params(sur.he_init(6))
+    r = st.rollout(net, seed=7, jumps=4, check_every=2, tol=1e-2, t0=200)
+    assert r["fallbacks"] == 2 and all(e > 1e-2 for e in r["errors"])
+    assert r["rollout_s"] > r["solver_s"]  # every segment charged the solver's time as well
+    r2 = st.rollout(net, seed=7, jumps=4, check_every=2, tol=float("inf"), t0=200)
+    assert r2["fallbacks"] == 0
+    assert abs(r2["errors"][0] - r["errors"][0]) < 1e-4
