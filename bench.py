@@ -288,6 +288,7 @@ def run_surrogate(args):
                      "kernel": "sur::k_conv (all convolutions of one forward)", "flops_per_launch": flops},
         "rollout": {"solver_ms": r["solver_s"] * 1e3, "rollout_ms": r["rollout_s"] * 1e3,
                     "fallbacks": r["fallbacks"], "phi_rel_l2_at_checks": r["errors"],
+                    "persistence_phi_rel_l2": r["persistence_errors"],
                     "forward_ms": ms_total, "conv_ms": ms_conv},
         "cpu_baseline": cpu,
     }
