@@ -181,14 +181,16 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
  *                     launch marches along z and runs one substep;
  *                 2 = fused tiles (D2Q9, cd_Q = 1): a launch runs plan[1]
  *                     substeps (1, 2, 3 or 5) of plan[2] x plan[2] tiles
- *                     (16 or 32) in LDS, halo 3 per substep;
+ *                     (16, 32, 48 or 64) in LDS, halo 3 per substep, when the
+ *                     staged tile fits a CU's 160 KiB of LDS;
  *   plan[1] fuse: substeps per launch, 1..5 (D2Q9), 1 (D3Q19);
  *   plan[2] bw:   D2Q9: columns per block, 64, 128 or 256 (256 with
  *                 HLB_F32_SHIFTED only), bw - 6*fuse >= 16;
  *                 D3Q19: threads per block, each owning two (x, y)
  *                 columns: 256 (16x32 columns), 512 (32x32) or 1024 (64x32,
  *                 HLB_F32_SHIFTED only);
- *   plan[3] seg:  rows (D2Q9) or planes (D3Q19) per block, >= 1.
+ *   plan[3] seg:  kind 1: rows (D2Q9) or planes (D3Q19) per block, >= 1;
+ *                 kind 2: threads per block, 256, 512 or 1024 (0 = 256).
  * hlb_create picks a plan from the lattice size; hlb_set_plan overrides it
  * (HLB_EINVAL if the plan cannot run this context).  hlb_set_params keeps a
  * user plan while it stays valid. */

@@ -47,6 +47,14 @@ template <> struct Tiles<D3Q19, float> {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// LDS bytes of the fused-tile substep kernel (phi, u*_x, u*_y staged with a
+// halo of 3M, h and the potential on the shrinking regions), and a CU's LDS.
+constexpr size_t kMaxLds = 163840;
+constexpr size_t fused_tile_lds(size_t es, int M, int TO) {
+  const size_t L0 = TO + 6 * M;
+  return es * (3 * L0 * L0 + (L0 - 2) * (L0 - 2) + (L0 - 4) * (L0 - 4));
+}
+
 struct Layout {
   size_t g[2], phi[2], u, io, part, out, total;
   int nblk_reduce;
@@ -365,13 +373,26 @@ struct Ops {
       else if constexpr (sizeof(T) == 4) march_bw<256>(c, k, M, c->plan.seg, src, dst);
     }
   }
+  // fused tiles: plan.bw is the tile edge, plan.seg the threads per block
+  // (0 means 256); combinations whose LDS exceeds a CU's are never launched
+  // (plan_valid rejects them)
+  template <int M, int TO, int NTH>
+  static void tile_launch(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
+    if constexpr (fused_tile_lds(sizeof(T), M, TO) <= kMaxLds) {
+      const dim3 grid(ceil_div(c->nx, TO), ceil_div(c->ny, TO));
+      if (k.advection == 1)
+        hipLaunchKernelGGL((k_ch_tile<T, M, TO, true, NTH>), grid, dim3(NTH), 0, c->stream, k, src,
+                           at<T>(c, c->lay.u), dst);
+      else
+        hipLaunchKernelGGL((k_ch_tile<T, M, TO, false, NTH>), grid, dim3(NTH), 0, c->stream, k, src,
+                           at<T>(c, c->lay.u), dst);
+    }
+  }
   template <int M, int TO>
   static void tile1(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
-    const dim3 grid(ceil_div(c->nx, TO), ceil_div(c->ny, TO));
-    if (k.advection == 1)
-      hipLaunchKernelGGL((k_ch_tile<T, M, TO, true>), grid, dim3(NT), 0, c->stream, k, src, at<T>(c, c->lay.u), dst);
-    else
-      hipLaunchKernelGGL((k_ch_tile<T, M, TO, false>), grid, dim3(NT), 0, c->stream, k, src, at<T>(c, c->lay.u), dst);
+    if (c->plan.seg == 1024) tile_launch<M, TO, 1024>(c, k, src, dst);
+    else if (c->plan.seg == 512) tile_launch<M, TO, 512>(c, k, src, dst);
+    else tile_launch<M, TO, 256>(c, k, src, dst);
   }
   template <int TO>
   static void tile_to(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
@@ -379,15 +400,15 @@ struct Ops {
       case 1: tile1<1, TO>(c, k, src, dst); break;
       case 2: tile1<2, TO>(c, k, src, dst); break;
       case 3: tile1<3, TO>(c, k, src, dst); break;
-      default:
-        if constexpr (sizeof(T) == 4 || TO == 16) tile1<5, TO>(c, k, src, dst);
-        break;
+      default: tile1<5, TO>(c, k, src, dst); break;
     }
   }
   // one fused-tile launch of M substeps
   static void tile(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
     if constexpr (L::D == 2) {
       if (c->plan.bw == 16) tile_to<16>(c, k, M, src, dst);
+      else if (c->plan.bw == 48) tile_to<48>(c, k, M, src, dst);
+      else if (c->plan.bw == 64) tile_to<64>(c, k, M, src, dst);
       else tile_to<32>(c, k, M, src, dst);
     }
   }
@@ -521,12 +542,16 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
       *why = "fused tile: fuse must be 1, 2, 3 or 5";
       return false;
     }
-    if (pl.bw != 16 && pl.bw != 32) {
-      *why = "fused tile: bw (tile edge) must be 16 or 32";
+    if (pl.bw != 16 && pl.bw != 32 && pl.bw != 48 && pl.bw != 64) {
+      *why = "fused tile: bw (tile edge) must be 16, 32, 48 or 64";
       return false;
     }
-    if (c->storage == HLB_F64 && pl.bw == 32 && pl.fuse == 5) {
-      *why = "fused tile: 32-site tiles of 5 substeps need float storage (LDS size)";
+    if (fused_tile_lds(c->storage == HLB_F64 ? 8 : 4, pl.fuse, pl.bw) > kMaxLds) {
+      *why = "fused tile: the staged tile of this edge and fuse exceeds the 160 KiB of LDS";
+      return false;
+    }
+    if (pl.seg != 0 && pl.seg != 256 && pl.seg != 512 && pl.seg != 1024) {
+      *why = "fused tile: seg (threads per block) must be 0 (256), 256, 512 or 1024";
       return false;
     }
     return true;
@@ -1048,11 +1073,12 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   }
   if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
     for (int fuse : {1, 2, 3, 5})
-      for (int to : {16, 32}) {
-        ChPlan pl{2, std::min(fuse, c->m == 4 ? 3 : c->m), to, 0};
-        std::string why;
-        if (fuse <= c->m && plan_valid(c, pl, &why)) cand.push_back(pl);
-      }
+      for (int to : {16, 32, 48, 64})
+        for (int nth : {256, 512, 1024}) {
+          ChPlan pl{2, std::min(fuse, c->m == 4 ? 3 : c->m), to, nth};
+          std::string why;
+          if (fuse <= c->m && plan_valid(c, pl, &why)) cand.push_back(pl);
+        }
     for (int fuse = 1; fuse <= std::min(c->m, 5); fuse++)
       for (int bw : {64, 128, 256})
         for (int seg : {8, 16, 32, 64, 128, 256}) {

@@ -122,10 +122,10 @@ __device__ __forceinline__ void tile_coords(int &bx, int &by, int &bz) {
   bz = lid / (gx * gy);
 }
 
-template <int D, typename T, int PX, int PY, int PZ>
+template <int D, typename T, int PX, int PY, int PZ, int NTH = NT>
 struct TileLoad {
   static constexpr int N = PX * PY * PZ;
-  static constexpr int K = (N + NT - 1) / NT;
+  static constexpr int K = (N + NTH - 1) / NTH;
   T v[K];
 
   __device__ __forceinline__ void issue(const T *__restrict__ field, const KParams &p, int gx0, int gy0, int gz0) {
@@ -136,8 +136,8 @@ struct TileLoad {
       const T *base = field + gx0 + nx * (gy0 + ny * (D == 3 ? gz0 : 0));
 #pragma unroll
       for (int k = 0; k < K; k++) {
-        const int i = threadIdx.x + k * NT;
-        if (N % NT == 0 || i < N) {
+        const int i = threadIdx.x + k * NTH;
+        if (N % NTH == 0 || i < N) {
           const int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
           v[k] = base[lx + nx * (ly + ny * lz)];
         }
@@ -147,8 +147,8 @@ struct TileLoad {
     const bool fast = nx >= PX && ny >= PY && (D == 2 || nz >= PZ);
 #pragma unroll
     for (int k = 0; k < K; k++) {
-      const int i = threadIdx.x + k * NT;
-      if (N % NT == 0 || i < N) {
+      const int i = threadIdx.x + k * NTH;
+      if (N % NTH == 0 || i < N) {
         const int lx = i % PX, ly = (i / PX) % PY, lz = i / (PX * PY);
         int gx, gy, gz = 0;
         if (fast) {
@@ -169,8 +169,8 @@ struct TileLoad {
     T *flat = &s[0][0][0];
 #pragma unroll
     for (int k = 0; k < K; k++) {
-      const int i = threadIdx.x + k * NT;
-      if (N % NT == 0 || i < N) flat[i] = v[k];
+      const int i = threadIdx.x + k * NTH;
+      if (N % NTH == 0 || i < N) flat[i] = v[k];
     }
   }
 };
@@ -834,9 +834,11 @@ __global__ void __launch_bounds__(BW) k_chm_batch(const SimDesc *__restrict__ si
 // a halo of 2, the diffusion potential with a halo of 1, then phi^{s+1},
 // written over phi^s in place (the last phase reads only h and the
 // potential).  Global traffic: phi and u* read once, phi' written once.
-template <typename T, int M, int TO, bool FLUX>
-__global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
-                                                T *__restrict__ phi_out) {
+// NTH threads per block (256, 512 or 1024): more waves per CU where the
+// LDS of a large tile admits only one or two blocks.
+template <typename T, int M, int TO, bool FLUX, int NTH>
+__global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
+                                                 T *__restrict__ phi_out) {
   constexpr int H = 3 * M;
   constexpr int L0 = TO + 2 * H;  // staged region edge
   __shared__ T sphi[1][L0][L0], sux[1][L0][L0], suy[1][L0][L0];
@@ -846,7 +848,7 @@ __global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__
   const int x0 = bx * TO, y0 = by * TO;
   const size_t ns = (size_t)p.ns;
   {
-    TileLoad<2, T, L0, L0, 1> lphi, lux, luy;
+    TileLoad<2, T, L0, L0, 1, NTH> lphi, lux, luy;
     lphi.issue(phi_in, p, x0 - H, y0 - H, 0);
     lux.issue(u, p, x0 - H, y0 - H, 0);
     luy.issue(u + ns, p, x0 - H, y0 - H, 0);
@@ -863,7 +865,7 @@ __global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__
     // input region of substep s: [3s, L0 - 3s) on both axes of the staged box
     const int lo = 3 * s;
     const int LH = L0 - 6 * s - 2;  // h region edge, origin lo + 1
-    for (int i = threadIdx.x; i < LH * LH; i += NT) {
+    for (int i = threadIdx.x; i < LH * LH; i += NTH) {
       const int y = lo + 1 + i / LH, x = lo + 1 + i % LH;
       const T pc = sphi[0][y][x];
       const T pw = sphi[0][y][x - 1], pe = sphi[0][y][x + 1];
@@ -886,7 +888,7 @@ __global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__
     }
     __syncthreads();
     const int LM = LH - 2;  // potential region edge, origin lo + 2
-    for (int i = threadIdx.x; i < LM * LM; i += NT) {
+    for (int i = threadIdx.x; i < LM * LM; i += NTH) {
       const int y = lo + 2 + i / LM, x = lo + 2 + i % LM;
       const int hy = y - 1, hx = x - 1;
       const T hc = sh[hy][hx];
@@ -896,7 +898,7 @@ __global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__
     }
     __syncthreads();
     const int LO = LM - 2;  // output region edge, origin lo + 3
-    for (int i = threadIdx.x; i < LO * LO; i += NT) {
+    for (int i = threadIdx.x; i < LO * LO; i += NTH) {
       const int y = lo + 3 + i / LO, x = lo + 3 + i % LO;
       const int my = y - 2, mx = x - 2;
       const T Lm = cQ * ((smu[my][mx + 1] + smu[my][mx - 1]) + (smu[my + 1][mx] + smu[my - 1][mx])) + cC * smu[my][mx];
@@ -904,7 +906,7 @@ __global__ void __launch_bounds__(NT) k_ch_tile(KParams p, const T *__restrict__
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < TO * TO; i += NT) {
+  for (int i = threadIdx.x; i < TO * TO; i += NTH) {
     const int ty = i / TO, tx = i % TO;
     const int x = x0 + tx, y = y0 + ty;
     if (x < p.nx && y < p.ny) phi_out[x + p.nx * y] = sphi[0][H + ty][H + tx];
