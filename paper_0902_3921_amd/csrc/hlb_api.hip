@@ -1064,12 +1064,24 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   std::vector<ChPlan> cand;
   cand.push_back(ChPlan{0, 1, 128, 64});
   if (c->lattice == HLB_D3Q19 && c->p.cd_Q == 1.0) {
-    for (int bw : {256, 512, 1024})
-      for (int seg : {8, 16, 32, 64, 128}) {
+    for (int bw : {256, 512, 1024}) {
+      std::vector<int> segs = {8, 16, 32, 64, 128};
+      // segment heights that make the block count just reach a multiple of
+      // the 256 CUs (one block per CU at 1024 threads)
+      const int txi = bw == 256 ? 16 : (bw == 512 ? 32 : 64);
+      const int cols = ceil_div(c->nx, txi - 6) * ceil_div(c->ny, 32 - 6);
+      for (int waves = 1; waves <= 4; waves++) {
+        const int nseg = std::max(1, (256 * waves) / std::max(1, cols));
+        segs.push_back(ceil_div(c->nz, nseg));
+      }
+      std::sort(segs.begin(), segs.end());
+      segs.erase(std::unique(segs.begin(), segs.end()), segs.end());
+      for (int seg : segs) {
         ChPlan pl{1, 1, bw, seg};
         std::string why;
         if (plan_valid(c, pl, &why)) cand.push_back(pl);
       }
+    }
   }
   if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
     for (int fuse : {1, 2, 3, 5})
