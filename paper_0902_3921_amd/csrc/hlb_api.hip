@@ -47,12 +47,12 @@ template <> struct Tiles<D3Q19, float> {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// LDS bytes of the fused-tile substep kernel (phi, u*_x, u*_y staged with a
-// halo of 3M, h and the potential on the shrinking regions), and a CU's LDS.
+// LDS bytes of the fused-tile substep kernel (phi, u*_x, u*_y, h and the
+// potential on the staged box of its geometry), and a CU's LDS.
 constexpr size_t kMaxLds = 163840;
 constexpr size_t fused_tile_lds(size_t es, int M, int TO) {
-  const size_t L0 = TO + 6 * M;
-  return es * (3 * L0 * L0 + (L0 - 2) * (L0 - 2) + (L0 - 4) * (L0 - 4));
+  const size_t V = 16 / es, L0 = TO + 6 * M, pitch = (L0 + 2 * V + V - 1) / V * V;
+  return 5 * L0 * pitch * es;
 }
 
 struct Layout {
@@ -378,6 +378,7 @@ struct Ops {
   // (plan_valid rejects them)
   template <int M, int TO, int NTH>
   static void tile_launch(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
+    static_assert(fused_tile_lds(sizeof(T), M, TO) == FusedTileGeom<T, M, TO>::LDS, "LDS formula");
     if constexpr (fused_tile_lds(sizeof(T), M, TO) <= kMaxLds) {
       const dim3 grid(ceil_div(c->nx, TO), ceil_div(c->ny, TO));
       if (k.advection == 1)

@@ -165,6 +165,17 @@ struct TileLoad {
     }
   }
 
+  // Writes the tile into a 2D LDS array with row pitch PITCH, element (x, y)
+  // at s[y * PITCH + OFFX + x].
+  template <int PITCH, int OFFX>
+  __device__ __forceinline__ void commit_pitched(T *s) const {
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      if (N % NTH == 0 || i < N) s[(i / PX) * PITCH + OFFX + i % PX] = v[k];
+    }
+  }
+
   __device__ __forceinline__ void commit(T (&s)[PZ][PY][PX]) const {
     T *flat = &s[0][0][0];
 #pragma unroll
@@ -827,6 +838,20 @@ __global__ void __launch_bounds__(BW) k_chm_batch(const SimDesc *__restrict__ si
     ch_march_body<T, M, BW, false>(lds, sd.p, tr.x0, ncol, tr.y0, y1, in, u + sd.u, out);
 }
 
+// Geometry of the fused-tile kernel: the staged box is L0 x L0 sites (the
+// tile plus a halo of 3M), stored in rows of FT_PITCH elements with FT_OFF
+// leading elements, so that each 16-byte vector of a row is aligned and the
+// neighbours at x - 1 and x + V of any vector are inside the row.
+template <typename T, int M, int TO>
+struct FusedTileGeom {
+  static constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
+  static constexpr int H = 3 * M;
+  static constexpr int L0 = TO + 2 * H;
+  static constexpr int OFF = V;
+  static constexpr int PITCH = ((L0 + 2 * V + V - 1) / V) * V;
+  static constexpr size_t LDS = 5ull * L0 * PITCH * sizeof(T);  // phi, u*_x, u*_y, h, potential
+};
+
 // M convection-diffusion substeps of one TO x TO tile in a single launch
 // (2D, standard 5-point Laplacian).  phi and u* are staged once with a halo
 // of 3M; substep s then works on a region that shrinks by 3 on every side
@@ -834,15 +859,20 @@ __global__ void __launch_bounds__(BW) k_chm_batch(const SimDesc *__restrict__ si
 // a halo of 2, the diffusion potential with a halo of 1, then phi^{s+1},
 // written over phi^s in place (the last phase reads only h and the
 // potential).  Global traffic: phi and u* read once, phi' written once.
-// NTH threads per block (256, 512 or 1024): more waves per CU where the
-// LDS of a large tile admits only one or two blocks.
+// Each thread computes V consecutive sites of a row per work item with
+// 16-byte LDS accesses; the vectors of a region are aligned down, so the
+// first and last of a row may extend past the region: those sites are
+// computed from stale values and written where nothing reads them again
+// (h and the potential outside the region are overwritten before their next
+// use, and phi outside the output region is no longer an input).
+// NTH threads per block (256, 512 or 1024).
 template <typename T, int M, int TO, bool FLUX, int NTH>
 __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
                                                  T *__restrict__ phi_out) {
-  constexpr int H = 3 * M;
-  constexpr int L0 = TO + 2 * H;  // staged region edge
-  __shared__ T sphi[1][L0][L0], sux[1][L0][L0], suy[1][L0][L0];
-  __shared__ T sh[L0 - 2][L0 - 2], smu[L0 - 4][L0 - 4];
+  using G = FusedTileGeom<T, M, TO>;
+  constexpr int V = G::V, H = G::H, L0 = G::L0, OFF = G::OFF, P = G::PITCH;
+  typedef T vec __attribute__((ext_vector_type(V)));
+  __shared__ __attribute__((aligned(16))) T sphi[L0 * P], sux[L0 * P], suy[L0 * P], sh[L0 * P], smu[L0 * P];
   int bx, by, bz;
   tile_coords(bx, by, bz);
   const int x0 = bx * TO, y0 = by * TO;
@@ -852,64 +882,111 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     lphi.issue(phi_in, p, x0 - H, y0 - H, 0);
     lux.issue(u, p, x0 - H, y0 - H, 0);
     luy.issue(u + ns, p, x0 - H, y0 - H, 0);
-    lphi.commit(sphi);
-    lux.commit(sux);
-    luy.commit(suy);
+    lphi.template commit_pitched<P, OFF>(sphi);
+    lux.template commit_pitched<P, OFF>(sux);
+    luy.template commit_pitched<P, OFF>(suy);
   }
   __syncthreads();
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
+  auto ld = [](const T *arr, int y, int x) { return *reinterpret_cast<const vec *>(arr + y * P + OFF + x); };
+  auto ld1 = [](const T *arr, int y, int x) { return arr[y * P + OFF + x]; };
+  auto st = [](T *arr, int y, int x, vec v) { *reinterpret_cast<vec *>(arr + y * P + OFF + x) = v; };
+  // the V-site neighbours to the west and east of a vector c with edge values w and e
+  auto west = [](vec c, T w) {
+    vec r;
+    r[0] = w;
+#pragma unroll
+    for (int j = 1; j < V; j++) r[j] = c[j - 1];
+    return r;
+  };
+  auto east = [](vec c, T e) {
+    vec r;
+#pragma unroll
+    for (int j = 0; j < V - 1; j++) r[j] = c[j + 1];
+    r[V - 1] = e;
+    return r;
+  };
 
 #pragma unroll
   for (int s = 0; s < M; s++) {
-    // input region of substep s: [3s, L0 - 3s) on both axes of the staged box
     const int lo = 3 * s;
-    const int LH = L0 - 6 * s - 2;  // h region edge, origin lo + 1
-    for (int i = threadIdx.x; i < LH * LH; i += NTH) {
-      const int y = lo + 1 + i / LH, x = lo + 1 + i % LH;
-      const T pc = sphi[0][y][x];
-      const T pw = sphi[0][y][x - 1], pe = sphi[0][y][x + 1];
-      const T pdn = sphi[0][y - 1][x], pup = sphi[0][y + 1][x];
-      const T uxc = sux[0][y][x], uxw = sux[0][y][x - 1], uxe = sux[0][y][x + 1];
-      const T uyc = suy[0][y][x], uyd = suy[0][y - 1][x], uyu = suy[0][y + 1][x];
-      T rhs;
-      if constexpr (!FLUX) {
-        const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
-        const T ty = pc * ((uyu - uyd) * T(0.5)) + uyc * (uyc > T(0) ? pc - pdn : pup - pc);
-        rhs = tx + ty;
-      } else {
-        const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
-        const T vyu = (uyc + uyu) * T(0.5), vyd = (uyd + uyc) * T(0.5);
-        const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
-        const T ty = (vyu > T(0) ? vyu * pc : vyu * pup) - (vyd > T(0) ? vyd * pdn : vyd * pc);
-        rhs = tx + ty;
+    // h on [lo + 1, L0 - lo - 1)^2
+    {
+      const int r0 = lo + 1, r1 = L0 - lo - 1;
+      const int xa = (r0 / V) * V, nq = (r1 - xa + V - 1) / V;
+      for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
+        const int y = r0 + i / nq, x = xa + V * (i % nq);
+        const vec pc = ld(sphi, y, x), pdn = ld(sphi, y - 1, x), pup = ld(sphi, y + 1, x);
+        const vec pw = west(pc, ld1(sphi, y, x - 1)), pe = east(pc, ld1(sphi, y, x + V));
+        const vec uxc = ld(sux, y, x);
+        const vec uxw = west(uxc, ld1(sux, y, x - 1)), uxe = east(uxc, ld1(sux, y, x + V));
+        const vec uyc = ld(suy, y, x), uyd = ld(suy, y - 1, x), uyu = ld(suy, y + 1, x);
+        vec h;
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          T rhs;
+          if constexpr (!FLUX) {
+            const T tx = pc[j] * ((uxe[j] - uxw[j]) * T(0.5)) + uxc[j] * (uxc[j] > T(0) ? pc[j] - pw[j] : pe[j] - pc[j]);
+            const T ty =
+                pc[j] * ((uyu[j] - uyd[j]) * T(0.5)) + uyc[j] * (uyc[j] > T(0) ? pc[j] - pdn[j] : pup[j] - pc[j]);
+            rhs = tx + ty;
+          } else {
+            const T vxe = (uxc[j] + uxe[j]) * T(0.5), vxw = (uxw[j] + uxc[j]) * T(0.5);
+            const T vyu = (uyc[j] + uyu[j]) * T(0.5), vyd = (uyd[j] + uyc[j]) * T(0.5);
+            const T tx = (vxe > T(0) ? vxe * pc[j] : vxe * pe[j]) - (vxw > T(0) ? vxw * pw[j] : vxw * pc[j]);
+            const T ty = (vyu > T(0) ? vyu * pc[j] : vyu * pup[j]) - (vyd > T(0) ? vyd * pdn[j] : vyd * pc[j]);
+            rhs = tx + ty;
+          }
+          h[j] = pc[j] - dt * rhs;
+        }
+        st(sh, y, x, h);
       }
-      sh[y - 1][x - 1] = pc - dt * rhs;
     }
     __syncthreads();
-    const int LM = LH - 2;  // potential region edge, origin lo + 2
-    for (int i = threadIdx.x; i < LM * LM; i += NTH) {
-      const int y = lo + 2 + i / LM, x = lo + 2 + i % LM;
-      const int hy = y - 1, hx = x - 1;
-      const T hc = sh[hy][hx];
-      const T Lh = cQ * ((sh[hy][hx + 1] + sh[hy][hx - 1]) + (sh[hy + 1][hx] + sh[hy - 1][hx])) + cC * hc;
-      const T ph = sphi[0][y][x];
-      smu[y - 2][x - 2] = a * hc + b * ph * ph * ph - kappa * Lh;
+    // diffusion potential on [lo + 2, L0 - lo - 2)^2
+    {
+      const int r0 = lo + 2, r1 = L0 - lo - 2;
+      const int xa = (r0 / V) * V, nq = (r1 - xa + V - 1) / V;
+      for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
+        const int y = r0 + i / nq, x = xa + V * (i % nq);
+        const vec hc = ld(sh, y, x), hdn = ld(sh, y - 1, x), hup = ld(sh, y + 1, x);
+        const vec hw = west(hc, ld1(sh, y, x - 1)), he = east(hc, ld1(sh, y, x + V));
+        const vec ph = ld(sphi, y, x);
+        vec mu;
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          const T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
+          mu[j] = a * hc[j] + b * ph[j] * ph[j] * ph[j] - kappa * Lh;
+        }
+        st(smu, y, x, mu);
+      }
     }
     __syncthreads();
-    const int LO = LM - 2;  // output region edge, origin lo + 3
-    for (int i = threadIdx.x; i < LO * LO; i += NTH) {
-      const int y = lo + 3 + i / LO, x = lo + 3 + i % LO;
-      const int my = y - 2, mx = x - 2;
-      const T Lm = cQ * ((smu[my][mx + 1] + smu[my][mx - 1]) + (smu[my + 1][mx] + smu[my - 1][mx])) + cC * smu[my][mx];
-      sphi[0][y][x] = sh[y - 1][x - 1] + dtg * Lm;
+    // phi^{s+1} on [lo + 3, L0 - lo - 3)^2
+    {
+      const int r0 = lo + 3, r1 = L0 - lo - 3;
+      const int xa = (r0 / V) * V, nq = (r1 - xa + V - 1) / V;
+      for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
+        const int y = r0 + i / nq, x = xa + V * (i % nq);
+        const vec mc = ld(smu, y, x), mdn = ld(smu, y - 1, x), mup = ld(smu, y + 1, x);
+        const vec mw = west(mc, ld1(smu, y, x - 1)), me = east(mc, ld1(smu, y, x + V));
+        const vec hc = ld(sh, y, x);
+        vec out;
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          const T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
+          out[j] = hc[j] + dtg * Lm;
+        }
+        st(sphi, y, x, out);
+      }
     }
     __syncthreads();
   }
   for (int i = threadIdx.x; i < TO * TO; i += NTH) {
     const int ty = i / TO, tx = i % TO;
     const int x = x0 + tx, y = y0 + ty;
-    if (x < p.nx && y < p.ny) phi_out[x + p.nx * y] = sphi[0][H + ty][H + tx];
+    if (x < p.nx && y < p.ny) phi_out[x + p.nx * y] = sphi[(H + ty) * P + OFF + H + tx];
   }
 }
 

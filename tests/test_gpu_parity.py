@@ -261,14 +261,18 @@ def test_substep_plans_agree(hlb, plan, storage):
     if storage == "f64" and plan[0] == 1 and plan[2] == 256:
         pytest.skip("needs float storage (LDS size)")
     if plan[0] == 2:
-        l0 = plan[2] + 6 * plan[1]
-        if (8 if storage == "f64" else 4) * (3 * l0 * l0 + (l0 - 2) ** 2 + (l0 - 4) ** 2) > 163840:
+        es = 8 if storage == "f64" else 4
+        v, l0 = 16 // es, plan[2] + 6 * plan[1]
+        pitch = -(-(l0 + 2 * v) // v) * v
+        if 5 * l0 * pitch * es > 163840:
             pytest.skip("the staged tile exceeds a CU's LDS in this storage")
     shape = (83, 150)
     phi = _drop(shape, 20, BASE) + synth.spinodal(shape, seed=5, amp=0.02)
     u0 = np.zeros((2,) + shape)
     u0[0], u0[1] = 0.01, -0.007
-    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=0.3, Q=2.5, advection=plan[3] % 2)
+    # both advection forms across the plans (fused tiles: by tile edge)
+    advection = (plan[2] // 16) % 2 if plan[0] == 2 else plan[3] % 2
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=0.3, Q=2.5, advection=advection)
     gpu.set_plan(*plan)
     assert gpu.plan == plan
     gpu.step(40)
