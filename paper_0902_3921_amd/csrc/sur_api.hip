@@ -41,8 +41,11 @@ void specs(const sur_config &c, LayerSpec s[NLAYER]) {
 }
 
 bool config_ok(const sur_config *c) {
-  return c && c->batch >= 1 && c->height >= 4 && c->width >= 4 && c->height % 4 == 0 && c->width % 4 == 0 &&
-         c->c0 >= 1 && c->c1 >= 1 && c->c2 >= 1 && c->scale[0] > 0 && c->scale[1] > 0 && c->scale[2] > 0;
+  if (!(c && c->batch >= 1 && c->height >= 4 && c->width >= 4 && c->height % 4 == 0 && c->width % 4 == 0 &&
+        c->c0 >= 1 && c->c1 >= 1 && c->c2 >= 1 && c->scale[0] > 0 && c->scale[1] > 0 && c->scale[2] > 0))
+    return false;
+  // the largest activation (full resolution, c1 + c0 channels) is indexed with 32-bit integers
+  return (long long)c->batch * c->height * c->width * (c->c0 + c->c1 + c->c2 + 3) < (1LL << 31);
 }
 
 // Activation and gradient buffers (float counts per image at their level).
@@ -238,8 +241,13 @@ void conv(sur_net *n, int l, int batch, View in, View out, bool transpose, View 
   const auto *frag = reinterpret_cast<const sur::bf16x8 *>(at<__bf16>(n, transpose ? L.frag_t[l] : L.frag_f[l]));
   const float *bias = transpose ? nullptr : at<float>(n, L.params) + L.b_off[l];
   const int relu = transpose ? 0 : s.relu;
-  const int ncg = nct >= 4 ? 4 : nct;  // 16-channel tiles per block
-  const dim3 grid(batch * cdiv(W, 16) * cdiv(H, 8), cdiv(nct, ncg));
+  // 16-channel tiles per block: 4 where that still gives two blocks per CU,
+  // fewer on the coarse levels of a small batch (more blocks, each staging
+  // the same input tile for fewer output channels)
+  const long long ptiles = (long long)batch * cdiv(W, 16) * cdiv(H, 8);
+  int ncg = nct >= 4 ? 4 : nct;
+  while (ncg > 1 && ptiles * cdiv(nct, ncg) < 512) ncg = ncg == 4 ? 2 : 1;
+  const dim3 grid((unsigned)ptiles, cdiv(nct, ncg));
 #define SUR_CONV(TAPS, NCT)                                                                                        \
   hipLaunchKernelGGL((sur::k_conv<TAPS, NCT>), grid, dim3(256), 0, n->stream, H, W, in, K, frag, nkc, nct, bias, \
                      out, N, relu, mask)
@@ -343,7 +351,7 @@ void backward(sur_net *n, int batch) {
     hipLaunchKernelGGL(sur::k_up_back, dim3(grid_for(npix_at(n, batch, 1) * c1)), dim3(256), 0, n->stream, batch, H,
                        W, view(n, G_U0, 0), view(n, G_D1B), c1);
     hipLaunchKernelGGL(sur::k_relu_mask, dim3(grid_for(npix_at(n, batch, 1) * c1)), dim3(256), 0, n->stream,
-                       npix_at(n, batch, 1), view(n, G_D1B), view(n, A_D1B), c1);
+                       (int)npix_at(n, batch, 1), view(n, G_D1B), view(n, A_D1B), c1);
   }
   wgrad(n, D1B, batch, view(n, A_D1A), view(n, G_D1B));
   conv(n, D1B, batch, view(n, G_D1B), view(n, G_D1A), true, view(n, A_D1A));
@@ -355,7 +363,7 @@ void backward(sur_net *n, int batch) {
     hipLaunchKernelGGL(sur::k_up_back, dim3(grid_for(npix_at(n, batch, 2) * c2)), dim3(256), 0, n->stream, batch, H,
                        W, view(n, G_U1, 0), view(n, G_B2B), c2);
     hipLaunchKernelGGL(sur::k_relu_mask, dim3(grid_for(npix_at(n, batch, 2) * c2)), dim3(256), 0, n->stream,
-                       npix_at(n, batch, 2), view(n, G_B2B), view(n, A_B2B), c2);
+                       (int)npix_at(n, batch, 2), view(n, G_B2B), view(n, A_B2B), c2);
   }
   wgrad(n, B2B, batch, view(n, A_B2A), view(n, G_B2B));
   conv(n, B2B, batch, view(n, G_B2B), view(n, G_B2A), true, view(n, A_B2A));
@@ -367,7 +375,7 @@ void backward(sur_net *n, int batch) {
     hipLaunchKernelGGL(sur::k_pool_back, dim3(grid_for(npix_at(n, batch, 1) * c1)), dim3(256), 0, n->stream, batch,
                        H, W, view(n, G_P1), view(n, G_U1, c2), c1, 1);
     hipLaunchKernelGGL(sur::k_relu_mask, dim3(grid_for(npix_at(n, batch, 1) * c1)), dim3(256), 0, n->stream,
-                       npix_at(n, batch, 1), view(n, G_U1, c2), view(n, U1, c2), c1);
+                       (int)npix_at(n, batch, 1), view(n, G_U1, c2), view(n, U1, c2), c1);
   }
   wgrad(n, E1B, batch, view(n, A_E1A), view(n, G_U1, c2));
   conv(n, E1B, batch, view(n, G_U1, c2), view(n, G_E1A), true, view(n, A_E1A));
@@ -378,7 +386,7 @@ void backward(sur_net *n, int batch) {
     hipLaunchKernelGGL(sur::k_pool_back, dim3(grid_for(npix_at(n, batch, 0) * c0)), dim3(256), 0, n->stream, batch,
                        H, W, view(n, G_P0), view(n, G_U0, c1), c0, 1);
     hipLaunchKernelGGL(sur::k_relu_mask, dim3(grid_for(npix_at(n, batch, 0) * c0)), dim3(256), 0, n->stream,
-                       npix_at(n, batch, 0), view(n, G_U0, c1), view(n, U0, c1), c0);
+                       (int)npix_at(n, batch, 0), view(n, G_U0, c1), view(n, U0, c1), c0);
   }
   wgrad(n, E0B, batch, view(n, A_E0A), view(n, G_U0, c1));
   conv(n, E0B, batch, view(n, G_U0, c1), view(n, G_E0A), true, view(n, A_E0A));

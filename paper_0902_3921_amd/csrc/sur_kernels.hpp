@@ -266,68 +266,63 @@ __global__ void __launch_bounds__(NT) k_bgrad_reduce(const float *__restrict__ p
 }
 
 // ------------------------------------------------------------- elementwise
+// The elementwise kernels below index with 32-bit integers: every tensor of
+// the network holds fewer than 2^31 elements (the host checks it).
+
 // 2x2 mean: out (H/2 x W/2) from in (H x W).
 __global__ void __launch_bounds__(NT) k_pool(int B, int H, int W, View in, View out, int C) {
   const int Ho = H / 2, Wo = W / 2;
-  const long long total = (long long)B * Ho * Wo * C;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < total; i += (long long)gridDim.x * NT) {
-    const int c = i % C;
-    const long long pix = i / C;
-    const int x = pix % Wo, y = (pix / Wo) % Ho, b = pix / ((long long)Wo * Ho);
-    auto at = [&](int yy, int xx) { return in.p[((size_t)(b * H + yy) * W + xx) * in.C + in.off + c]; };
-    const float s = (at(2 * y, 2 * x) + at(2 * y, 2 * x + 1)) + (at(2 * y + 1, 2 * x) + at(2 * y + 1, 2 * x + 1));
-    out.p[(size_t)pix * out.C + out.off + c] = 0.25f * s;
+  const int total = B * Ho * Wo * C;
+  for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
+    const int c = i % C, pix = i / C;
+    const int x = pix % Wo, y = (pix / Wo) % Ho, b = pix / (Wo * Ho);
+    const float *r0 = in.p + ((b * H + 2 * y) * W + 2 * x) * in.C + in.off + c;
+    const float *r1 = r0 + W * in.C;
+    const float s = (r0[0] + r0[in.C]) + (r1[0] + r1[in.C]);
+    out.p[pix * out.C + out.off + c] = 0.25f * s;
   }
 }
 
 // Adjoint of the 2x2 mean: din[y][x] (+)= dout[y/2][x/2] / 4 (H, W of din).
 __global__ void __launch_bounds__(NT) k_pool_back(int B, int H, int W, View dout, View din, int C, int accumulate) {
-  const long long total = (long long)B * H * W * C;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < total; i += (long long)gridDim.x * NT) {
-    const int c = i % C;
-    const long long pix = i / C;
-    const int x = pix % W, y = (pix / W) % H, b = pix / ((long long)W * H);
-    const float g = 0.25f * dout.p[((size_t)(b * (H / 2) + y / 2) * (W / 2) + x / 2) * dout.C + dout.off + c];
-    float &d = din.p[(size_t)pix * din.C + din.off + c];
+  const int total = B * H * W * C;
+  for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
+    const int c = i % C, pix = i / C;
+    const int x = pix % W, y = (pix / W) % H, b = pix / (W * H);
+    const float g = 0.25f * dout.p[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * dout.C + dout.off + c];
+    float &d = din.p[pix * din.C + din.off + c];
     d = accumulate ? d + g : g;
   }
 }
 
 // Nearest 2x upsampling: out (H x W) from in (H/2 x W/2).
 __global__ void __launch_bounds__(NT) k_up(int B, int H, int W, View in, View out, int C) {
-  const long long total = (long long)B * H * W * C;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < total; i += (long long)gridDim.x * NT) {
-    const int c = i % C;
-    const long long pix = i / C;
-    const int x = pix % W, y = (pix / W) % H, b = pix / ((long long)W * H);
-    out.p[(size_t)pix * out.C + out.off + c] =
-        in.p[((size_t)(b * (H / 2) + y / 2) * (W / 2) + x / 2) * in.C + in.off + c];
+  const int total = B * H * W * C;
+  for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
+    const int c = i % C, pix = i / C;
+    const int x = pix % W, y = (pix / W) % H, b = pix / (W * H);
+    out.p[pix * out.C + out.off + c] = in.p[((b * (H / 2) + y / 2) * (W / 2) + x / 2) * in.C + in.off + c];
   }
 }
 
 // Adjoint of the upsampling: din[y][x] = sum of the 2x2 block of dout (H, W of din).
 __global__ void __launch_bounds__(NT) k_up_back(int B, int H, int W, View dout, View din, int C) {
-  const long long total = (long long)B * H * W * C;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < total; i += (long long)gridDim.x * NT) {
-    const int c = i % C;
-    const long long pix = i / C;
-    const int x = pix % W, y = (pix / W) % H, b = pix / ((long long)W * H);
-    const int W2 = 2 * W;
-    auto at = [&](int yy, int xx) {
-      return dout.p[((size_t)(b * 2 * H + yy) * W2 + xx) * dout.C + dout.off + c];
-    };
-    din.p[(size_t)pix * din.C + din.off + c] =
-        (at(2 * y, 2 * x) + at(2 * y, 2 * x + 1)) + (at(2 * y + 1, 2 * x) + at(2 * y + 1, 2 * x + 1));
+  const int total = B * H * W * C;
+  for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
+    const int c = i % C, pix = i / C;
+    const int x = pix % W, y = (pix / W) % H, b = pix / (W * H);
+    const float *r0 = dout.p + ((b * 2 * H + 2 * y) * (2 * W) + 2 * x) * dout.C + dout.off + c;
+    const float *r1 = r0 + 2 * W * dout.C;
+    din.p[pix * din.C + din.off + c] = (r0[0] + r0[dout.C]) + (r1[0] + r1[dout.C]);
   }
 }
 
-// d *= (a > 0), elementwise over B H W pixels and C channels.
-__global__ void __launch_bounds__(NT) k_relu_mask(long long npix, View d, View a, int C) {
-  const long long total = npix * C;
-  for (long long i = blockIdx.x * (long long)NT + threadIdx.x; i < total; i += (long long)gridDim.x * NT) {
-    const int c = i % C;
-    const long long pix = i / C;
-    if (!(a.p[(size_t)pix * a.C + a.off + c] > 0.f)) d.p[(size_t)pix * d.C + d.off + c] = 0.f;
+// d *= (a > 0), elementwise over npix pixels and C channels.
+__global__ void __launch_bounds__(NT) k_relu_mask(int npix, View d, View a, int C) {
+  const int total = npix * C;
+  for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
+    const int c = i % C, pix = i / C;
+    if (!(a.p[pix * a.C + a.off + c] > 0.f)) d.p[pix * d.C + d.off + c] = 0.f;
   }
 }
 
