@@ -129,6 +129,16 @@ def run_gpu(name, steps, warmup, plan=None):
     sim, secs, stats = timed(kw, plan)
     m = sim.m
     plan = sim.plan
+    # host transfers of the boundary (FP64 host arrays): one hlb_init_fields
+    # (upload + equilibrium kernel) and one hlb_get_fields (readout kernel +
+    # download), for the PCIe-inclusive rate of a run of `steps` steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.init(phi0)
+    t_init = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sim.fields()
+    t_fields = time.perf_counter() - t0
     # per-kernel durations from HIP events on the library's stream
     nprof = max(20, min(200, steps))
     ms_lb, ms_ch = sim.step_timed(nprof)
@@ -158,6 +168,8 @@ def run_gpu(name, steps, warmup, plan=None):
     return {
         "shape": shape, "storage": storage, "desc": desc, "m": m, "ns": ns, "secs": secs,
         "mlups": mlups, "mlups_standard": ns * steps / secs_sc / 1e6, "stats": stats, "plan": plan,
+        "host_io": {"init_ms": t_init * 1e3, "get_fields_ms": t_fields * 1e3,
+                    "pcie_inclusive_mlups": ns * steps / (secs + t_init + t_fields) / 1e6},
         "kernels": {"lb": {"name": names[0], "us_per_launch": t_lb * 1e6, "bytes_per_lu": lb_b,
                            "gbs": lb_b * ns / t_lb / 1e9},
                     "ch": {"name": names[1], "us_per_launch": t_ch * 1e6, "launches_per_step": ch_launches,
@@ -471,6 +483,7 @@ def main():
                      "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": kd["gbs"] / copy_gbs},
         "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
         "mlups_standard_stencil": r["mlups_standard"],
+        "host_io": r.get("host_io"),
         "kernels": r["kernels"],
         "check": {k: r["stats"][k] for k in ("finite", "mass", "umax", "umax_sim") if k in r["stats"]},
         "cpu_baseline": cpu,
