@@ -70,9 +70,16 @@ def generate(n_traj: int, pairs_per_traj: int = 8, group: int = 250, seed0: int 
     return snaps
 
 
-def train(net, snaps, iters: int, batch: int, lr: float, seed: int = 0, log=print, log_every: int = 200):
+def train(net, snaps, iters: int, batch: int, lr: float, seed: int = 0, log=print, log_every: int = 200,
+          pushforward: float = 0.0):
     """Adam on random (state, state + JUMP) pairs, cosine learning-rate decay
-    from lr to lr / 100.  Returns the list of (iteration, loss)."""
+    from lr to lr / 100.  With probability `pushforward` (after the first
+    third of the iterations) an iteration instead takes the network's own
+    prediction of a state one jump ahead as input and the state two jumps
+    ahead as target, without a gradient through the first jump (the
+    "pushforward" training of Brandstetter, Worrall and Welling), so that the
+    network learns to correct the errors it makes.  Returns the list of
+    (iteration, loss)."""
     import torch
 
     n_traj, n_snap = snaps.shape[0], snaps.shape[1]
@@ -82,10 +89,15 @@ def train(net, snaps, iters: int, batch: int, lr: float, seed: int = 0, log=prin
     x = torch.empty((batch, SIZE, SIZE, 3), dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
     for it in range(iters):
+        push = it >= iters // 3 and float(torch.rand((), generator=gen)) < pushforward
         ti = torch.randint(0, n_traj, (batch,), generator=gen)
-        si = torch.randint(0, n_snap - 1, (batch,), generator=gen)
+        si = torch.randint(0, n_snap - (2 if push else 1), (batch,), generator=gen)
         x.copy_(snaps[ti.cuda(), si.cuda()])
-        y.copy_(snaps[ti.cuda(), (si + 1).cuda()])
+        if push:
+            net.forward(x, x)
+            y.copy_(snaps[ti.cuda(), (si + 2).cuda()])
+        else:
+            y.copy_(snaps[ti.cuda(), (si + 1).cuda()])
         rate = lr * (0.01 + 0.99 * 0.5 * (1 + np.cos(np.pi * it / iters)))
         if it % log_every == 0 or it == iters - 1:
             loss = net.loss_grad(x, y)
@@ -171,6 +183,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rollout-seed", type=int, default=100000)
+    ap.add_argument("--pushforward", type=float, default=0.5)
     args = ap.parse_args(argv)
 
     import torch
@@ -185,7 +198,7 @@ def main(argv=None):
     print(f"data: {tuple(snaps.shape)} in {time.perf_counter() - t0:.0f} s", flush=True)
     net = sur.Surrogate(batch=args.batch)
     net.set_params(sur.he_init(args.seed))
-    hist = train(net, snaps, args.iters, args.batch, args.lr, args.seed)
+    hist = train(net, snaps, args.iters, args.batch, args.lr, args.seed, pushforward=args.pushforward)
     params = net.params()
     del snaps
     test = sur.Surrogate(batch=1)
@@ -193,6 +206,7 @@ def main(argv=None):
     r = rollout(test, args.rollout_seed)
     free = rollout(test, args.rollout_seed, tol=float("inf"))
     meta = dict(trajectories=args.trajectories, pairs=args.pairs, iters=args.iters, batch=args.batch, lr=args.lr,
+                pushforward=args.pushforward,
                 seed=args.seed, final_loss=hist[-1][1], rollout_errors=np.array(r["errors"]),
                 free_rollout_errors=np.array(free["errors"]), loss_history=np.array(hist),
                 recipe="spinodal 256x256 D2Q9 FP32, a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1 N=0.3 Q=2.5, "
