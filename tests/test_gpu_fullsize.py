@@ -53,3 +53,41 @@ def test_benchmark_workload_full_size(hlb, name, steps, stencil):
     d = {k: float(np.abs(g[k] - r[k]).max()) for k in ("n", "u", "phi")}
     print(f"max differences {d}", flush=True)
     assert max(d.values()) <= 2e-6, d
+
+
+@pytest.mark.parametrize("shape,base", [((16384, 16384), (256, 256)), ((512, 512, 512), (128, 128, 128))])
+def test_maximum_size_lattices(hlb, shape, base):
+    """Lattices whose population arrays exceed 2^31 elements (q * sites =
+    2.4e9 and 2.5e9), so any 32-bit population index would overflow.  The
+    initial phi repeats a seeded block, so the periodic solution repeats it
+    too: after a few steps every block of the big lattice must equal the
+    oracle's run on the single block (and, computed by the same formulas,
+    every block equals every other bit for bit)."""
+    import bench
+    import synth
+
+    d = len(shape)
+    kw = dict(bench.BASE, N=0.3, Q=2.5) if d == 2 else dict(bench.BASE, N=1 / 6, Q=1 / 3)
+    block = synth.spinodal(base, seed=11, amp=0.01)
+    reps = tuple(s // b for s, b in zip(shape, base))
+    sim = hlb.Sim(shape, "f32", **kw)
+    sim.init(np.tile(block, reps))
+    sim.autotune()
+    steps = 3 if d == 2 else 2
+    sim.step(steps)
+    print(f"{shape}: plan {sim.plan}, {steps} steps", flush=True)
+    g = sim.fields()
+    sim.close()
+    o = orc.Oracle(base, m=hlb.check_params(d - 2, **kw), **kw)
+    o.init(block)
+    o.step(steps)
+    r = o.fields()
+    for k in ("n", "phi"):
+        big = g[k].reshape(sum(((n, s) for n, s in zip(reps, base)), ()))
+        first = big[(0, slice(None)) * d]
+        # every block equals the first, bit for bit
+        axes = tuple(range(0, 2 * d, 2))
+        assert np.array_equal(big.max(axis=axes), big.min(axis=axes)), k
+        assert float(np.abs(first - r[k]).max()) <= 2e-6, k
+    gu = g["u"][0].reshape(sum(((n, s) for n, s in zip(reps, base)), ()))
+    assert float(np.abs(gu[(0, slice(None)) * d] - r["u"][0]).max()) <= 2e-6
