@@ -47,12 +47,15 @@ template <> struct Tiles<D3Q19, float> {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// LDS bytes of the fused-tile substep kernel (phi, u*_x, u*_y, h and the
-// potential on the staged box of its geometry), and a CU's LDS.
+// LDS bytes of the fused-tile substep kernel (two rotating arrays for phi, h
+// and the potential, and u*_x, u*_y, on the staged box of its geometry: rows
+// TO + 6M, columns TO plus a halo of 3M rounded up to 16-byte vectors on
+// each side, plus a vector of padding on each side), and a CU's LDS.
 constexpr size_t kMaxLds = 163840;
 constexpr size_t fused_tile_lds(size_t es, int M, int TO) {
-  const size_t V = 16 / es, L0 = TO + 6 * M, pitch = (L0 + 2 * V + V - 1) / V * V;
-  return 5 * L0 * pitch * es;
+  const size_t V = 16 / es, H = 3 * M, HA = (H + V - 1) / V * V;
+  const size_t rows = TO + 2 * H, pitch = TO + 2 * HA + 2 * V;
+  return 4 * rows * pitch * es;
 }
 
 struct Layout {

@@ -98,6 +98,25 @@ __device__ __forceinline__ int wrap1(int v, int n) {
   return v >= n ? v - n : v;
 }
 
+// Upwind terms of the advection half-step (Sec. 2.3) without a branch.
+// Written as a select between two neighbour values, the compiler moves each
+// neighbour's LDS load into its own divergent branch and waits for it there,
+// which serialises two LDS latencies per term; selecting on the velocity
+// instead issues both loads together.  For finite values the results equal
+// the selected forms up to the order of rounding in a fused multiply-add.
+// u (c - m) where u > 0, else u (p - c)  (one-sided difference upwind of u)
+template <typename T>
+__device__ __forceinline__ T upwind_diff(T u, T m, T c, T p) {
+  const bool pos = u > T(0);
+  return (pos ? u : T(0)) * (c - m) + (pos ? T(0) : u) * (p - c);
+}
+// v l where v > 0, else v r  (face flux of the upwind cell value)
+template <typename T>
+__device__ __forceinline__ T upwind_flux(T v, T l, T r) {
+  const bool pos = v > T(0);
+  return (pos ? v : T(0)) * l + (pos ? T(0) : v) * r;
+}
+
 // Threads per block of every stencil kernel.
 constexpr int NT = 256;
 
@@ -727,10 +746,11 @@ __device__ __forceinline__ void ch_march_body(MarchLds<T, M, BW> &lds, const KPa
       quy[k] = uy_g[g];
     }
   }
+  int slot = 0;                 // (t - t0) mod R, the ring row of input row t
+  int rq = row_of(t0 + 2);      // lattice row of t + 2, the next refill
   // one iteration: input row t from queue slot k (parity of the published rows = k)
   auto iterate = [&](const int t, const int k) {
     const int par = k;
-    const int slot = (t - t0) % R;
     // publish last iteration's rows and the new u* row
     sux[slot][c] = qux[k];
     suy[slot][c] = quy[k];
@@ -742,18 +762,20 @@ __device__ __forceinline__ void ch_march_body(MarchLds<T, M, BW> &lds, const KPa
     }
     carry[0] = qphi[k];  // phi^0 row t
     if (t + 2 < t1) {    // refill the slot with row t + 2
-      const int g = gx + nx * row_of(t + 2);
+      const int g = gx + nx * rq;
       qphi[k] = phi_in[g];
       qux[k] = ux_g[g];
       quy[k] = uy_g[g];
     }
+    rq = rq + 1 == ny ? 0 : rq + 1;
     __syncthreads();
     T last = T(0);
     // substeps in reverse order: substep s reads carry[s] before substep s-1 replaces it
 #pragma unroll
     for (int s = M - 1; s >= 0; s--) {
       // u* rows t-4s-2 (below), t-4s-1 (centre), t-4s (above) of the ring
-      int kc = (t - t0 - 4 * s - 1) % R;
+      // (4s + 1 < R, so one correction brings the ring row into [0, R))
+      int kc = slot - 4 * s - 1;
       kc += kc < 0 ? R : 0;
       const int kd = kc == 0 ? R - 1 : kc - 1, ku = kc == R - 1 ? 0 : kc + 1;
       // advection half-step at row t-4s-1
@@ -763,14 +785,14 @@ __device__ __forceinline__ void ch_march_body(MarchLds<T, M, BW> &lds, const KPa
       const T uyc = suy[kc][c], uyd = suy[kd][c], uyu = suy[ku][c];
       T rhs;
       if constexpr (!FLUX) {
-        const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
-        const T ty = pc * ((uyu - uyd) * T(0.5)) + uyc * (uyc > T(0) ? pc - pdn : pup - pc);
+        const T tx = pc * ((uxe - uxw) * T(0.5)) + upwind_diff(uxc, pw, pc, pe);
+        const T ty = pc * ((uyu - uyd) * T(0.5)) + upwind_diff(uyc, pdn, pc, pup);
         rhs = tx + ty;
       } else {
         const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
         const T vyu = (uyc + uyu) * T(0.5), vyd = (uyd + uyc) * T(0.5);
-        const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
-        const T ty = (vyu > T(0) ? vyu * pc : vyu * pup) - (vyd > T(0) ? vyd * pdn : vyd * pc);
+        const T tx = upwind_flux(vxe, pc, pe) - upwind_flux(vxw, pw, pc);
+        const T ty = upwind_flux(vyu, pc, pup) - upwind_flux(vyd, pdn, pc);
         rhs = tx + ty;
       }
       const T hn = pc - dt * rhs;
@@ -795,6 +817,7 @@ __device__ __forceinline__ void ch_march_body(MarchLds<T, M, BW> &lds, const KPa
     }
     const int yo = t - 4 * M + 1;  // row of the last substep's output
     if (col_out && yo >= y0 && yo < y1) phi_out[gx + nx * yo] = last;
+    slot = slot + 1 == R ? 0 : slot + 1;
   };
   // unrolled by two so the queue slot and the parity are static
   for (int t = t0; t < t1; t += 2) {
@@ -838,53 +861,108 @@ __global__ void __launch_bounds__(BW) k_chm_batch(const SimDesc *__restrict__ si
     ch_march_body<T, M, BW, false>(lds, sd.p, tr.x0, ncol, tr.y0, y1, in, u + sd.u, out);
 }
 
-// Geometry of the fused-tile kernel: the staged box is L0 x L0 sites (the
-// tile plus a halo of 3M), stored in rows of FT_PITCH elements with FT_OFF
-// leading elements, so that each 16-byte vector of a row is aligned and the
-// neighbours at x - 1 and x + V of any vector are inside the row.
+// Geometry of the fused-tile kernel.  The staged box holds the tile plus a
+// halo of H = 3M rows; in x the halo is rounded up to whole 16-byte vectors
+// (HA), so that the box starts on a vector boundary of the lattice row and
+// is staged and stored with 16-byte accesses.  Rows have PITCH elements with
+// OFF leading ones, so that each vector of a row is aligned and the
+// neighbours at x - 1 and x + V of any vector of the box are inside the row.
+// Four arrays: two for phi, h and the diffusion potential, which rotate
+// (see k_ch_tile), and u*_x, u*_y.
 template <typename T, int M, int TO>
 struct FusedTileGeom {
   static constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
   static constexpr int H = 3 * M;
-  static constexpr int L0 = TO + 2 * H;
+  static constexpr int HA = (H + V - 1) / V * V;
+  static constexpr int DX = HA - H;     // column of the H-halo box's origin
+  static constexpr int L0 = TO + 2 * H;  // staged rows
+  static constexpr int LW = TO + 2 * HA;  // staged columns, a multiple of V
   static constexpr int OFF = V;
-  static constexpr int PITCH = ((L0 + 2 * V + V - 1) / V) * V;
-  static constexpr size_t LDS = 5ull * L0 * PITCH * sizeof(T);  // phi, u*_x, u*_y, h, potential
+  static constexpr int PITCH = LW + 2 * V;
+  static constexpr size_t LDS = 4ull * L0 * PITCH * sizeof(T);
+};
+
+// Rows [gy0, gy0 + NR) x columns [gx0, gx0 + NC * V) of a periodic 2D field
+// staged in 16-byte vectors: issue() puts a thread's loads in flight,
+// commit() writes them into an LDS array of row pitch P (column c at
+// OFF + c).  gx0 is a multiple of V.  With `whole` (nx a multiple of V and
+// an aligned field) every vector lies inside one lattice row, so one wrap
+// per vector suffices; otherwise each element wraps on its own.
+template <typename T, int NR, int NC, int NTH>
+struct RowStage {
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int N = NR * NC;
+  static constexpr int K = (N + NTH - 1) / NTH;
+  typedef T vec __attribute__((ext_vector_type(V)));
+  vec v[K];
+
+  __device__ __forceinline__ void issue(const T *__restrict__ f, int nx, int ny, int gx0, int gy0, bool whole) {
+    const bool one = nx >= NC * V && ny >= NR;  // the box wraps at most once per axis
+    auto wrap = [one](int a, int n) { return one ? wrap1(a, n) : wrapc(a, n); };
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      if (N % NTH == 0 || i < N) {
+        const int r = i / NC, c = i % NC;
+        const T *row = f + (size_t)nx * wrap(gy0 + r, ny);
+        if (whole) {
+          v[k] = *reinterpret_cast<const vec *>(row + wrap(gx0 + V * c, nx));
+        } else {
+#pragma unroll
+          for (int j = 0; j < V; j++) v[k][j] = row[wrap(gx0 + V * c + j, nx)];
+        }
+      }
+    }
+  }
+  template <int P, int OFF>
+  __device__ __forceinline__ void commit(T *s) const {
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      if (N % NTH == 0 || i < N) *reinterpret_cast<vec *>(s + (i / NC) * P + OFF + V * (i % NC)) = v[k];
+    }
+  }
 };
 
 // M convection-diffusion substeps of one TO x TO tile in a single launch
 // (2D, standard 5-point Laplacian).  phi and u* are staged once with a halo
 // of 3M; substep s then works on a region that shrinks by 3 on every side
 // (its output region is the next substep's input), entirely in LDS: h with
-// a halo of 2, the diffusion potential with a halo of 1, then phi^{s+1},
-// written over phi^s in place (the last phase reads only h and the
-// potential).  Global traffic: phi and u* read once, phi' written once.
+// a halo of 2, the diffusion potential with a halo of 1, then phi^{s+1}.
+// Global traffic: phi and u* read once, phi' written once.
+// Two arrays A and B hold phi, h and the potential: with phi^s in A, h goes
+// to B, the potential overwrites phi^s in A (its phase reads phi only at
+// the site it writes) and phi^{s+1} overwrites h in B (likewise), after
+// which A and B swap roles.
 // Each thread computes V consecutive sites of a row per work item with
 // 16-byte LDS accesses; the vectors of a region are aligned down, so the
 // first and last of a row may extend past the region: those sites are
 // computed from stale values and written where nothing reads them again
-// (h and the potential outside the region are overwritten before their next
-// use, and phi outside the output region is no longer an input).
+// (outside the region that the next phase reads).
 // NTH threads per block (256, 512 or 1024).
 template <typename T, int M, int TO, bool FLUX, int NTH>
 __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
                                                  T *__restrict__ phi_out) {
   using G = FusedTileGeom<T, M, TO>;
-  constexpr int V = G::V, H = G::H, L0 = G::L0, OFF = G::OFF, P = G::PITCH;
+  constexpr int V = G::V, H = G::H, HA = G::HA, DX = G::DX, L0 = G::L0, LW = G::LW, OFF = G::OFF, P = G::PITCH;
   typedef T vec __attribute__((ext_vector_type(V)));
-  __shared__ __attribute__((aligned(16))) T sphi[L0 * P], sux[L0 * P], suy[L0 * P], sh[L0 * P], smu[L0 * P];
+  __shared__ __attribute__((aligned(16))) T sA[L0 * P], sB[L0 * P], sux[L0 * P], suy[L0 * P];
   int bx, by, bz;
   tile_coords(bx, by, bz);
   const int x0 = bx * TO, y0 = by * TO;
+  const int nx = p.nx, ny = p.ny;
   const size_t ns = (size_t)p.ns;
+  auto aligned = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  // nx a multiple of V keeps every row start (and so every vector) aligned
+  const bool whole = nx % V == 0 && aligned(phi_in) && aligned(u) && aligned(u + ns) && aligned(phi_out);
   {
-    TileLoad<2, T, L0, L0, 1, NTH> lphi, lux, luy;
-    lphi.issue(phi_in, p, x0 - H, y0 - H, 0);
-    lux.issue(u, p, x0 - H, y0 - H, 0);
-    luy.issue(u + ns, p, x0 - H, y0 - H, 0);
-    lphi.template commit_pitched<P, OFF>(sphi);
-    lux.template commit_pitched<P, OFF>(sux);
-    luy.template commit_pitched<P, OFF>(suy);
+    RowStage<T, L0, LW / V, NTH> lphi, lux, luy;
+    lphi.issue(phi_in, nx, ny, x0 - HA, y0 - H, whole);
+    lux.issue(u, nx, ny, x0 - HA, y0 - H, whole);
+    luy.issue(u + ns, nx, ny, x0 - HA, y0 - H, whole);
+    lphi.template commit<P, OFF>(sA);
+    lux.template commit<P, OFF>(sux);
+    luy.template commit<P, OFF>(suy);
   }
   __syncthreads();
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
@@ -910,15 +988,17 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
 
 #pragma unroll
   for (int s = 0; s < M; s++) {
+    T *const sp = s % 2 == 0 ? sA : sB;  // phi^s, then the potential
+    T *const sq = s % 2 == 0 ? sB : sA;  // h, then phi^{s+1}
     const int lo = 3 * s;
-    // h on [lo + 1, L0 - lo - 1)^2
+    // h on rows [lo + 1, L0 - lo - 1), columns DX + the same range
     {
       const int r0 = lo + 1, r1 = L0 - lo - 1;
-      const int xa = (r0 / V) * V, nq = (r1 - xa + V - 1) / V;
+      const int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
       for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
         const int y = r0 + i / nq, x = xa + V * (i % nq);
-        const vec pc = ld(sphi, y, x), pdn = ld(sphi, y - 1, x), pup = ld(sphi, y + 1, x);
-        const vec pw = west(pc, ld1(sphi, y, x - 1)), pe = east(pc, ld1(sphi, y, x + V));
+        const vec pc = ld(sp, y, x), pdn = ld(sp, y - 1, x), pup = ld(sp, y + 1, x);
+        const vec pw = west(pc, ld1(sp, y, x - 1)), pe = east(pc, ld1(sp, y, x + V));
         const vec uxc = ld(sux, y, x);
         const vec uxw = west(uxc, ld1(sux, y, x - 1)), uxe = east(uxc, ld1(sux, y, x + V));
         const vec uyc = ld(suy, y, x), uyd = ld(suy, y - 1, x), uyu = ld(suy, y + 1, x);
@@ -940,53 +1020,64 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
           }
           h[j] = pc[j] - dt * rhs;
         }
-        st(sh, y, x, h);
+        st(sq, y, x, h);
       }
     }
     __syncthreads();
-    // diffusion potential on [lo + 2, L0 - lo - 2)^2
+    // diffusion potential on [lo + 2, L0 - lo - 2), over phi^s
     {
       const int r0 = lo + 2, r1 = L0 - lo - 2;
-      const int xa = (r0 / V) * V, nq = (r1 - xa + V - 1) / V;
+      const int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
       for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
         const int y = r0 + i / nq, x = xa + V * (i % nq);
-        const vec hc = ld(sh, y, x), hdn = ld(sh, y - 1, x), hup = ld(sh, y + 1, x);
-        const vec hw = west(hc, ld1(sh, y, x - 1)), he = east(hc, ld1(sh, y, x + V));
-        const vec ph = ld(sphi, y, x);
+        const vec hc = ld(sq, y, x), hdn = ld(sq, y - 1, x), hup = ld(sq, y + 1, x);
+        const vec hw = west(hc, ld1(sq, y, x - 1)), he = east(hc, ld1(sq, y, x + V));
+        const vec ph = ld(sp, y, x);
         vec mu;
 #pragma unroll
         for (int j = 0; j < V; j++) {
           const T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
           mu[j] = a * hc[j] + b * ph[j] * ph[j] * ph[j] - kappa * Lh;
         }
-        st(smu, y, x, mu);
+        st(sp, y, x, mu);
       }
     }
     __syncthreads();
-    // phi^{s+1} on [lo + 3, L0 - lo - 3)^2
+    // phi^{s+1} on [lo + 3, L0 - lo - 3), over h
     {
       const int r0 = lo + 3, r1 = L0 - lo - 3;
-      const int xa = (r0 / V) * V, nq = (r1 - xa + V - 1) / V;
+      const int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
       for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
         const int y = r0 + i / nq, x = xa + V * (i % nq);
-        const vec mc = ld(smu, y, x), mdn = ld(smu, y - 1, x), mup = ld(smu, y + 1, x);
-        const vec mw = west(mc, ld1(smu, y, x - 1)), me = east(mc, ld1(smu, y, x + V));
-        const vec hc = ld(sh, y, x);
+        const vec mc = ld(sp, y, x), mdn = ld(sp, y - 1, x), mup = ld(sp, y + 1, x);
+        const vec mw = west(mc, ld1(sp, y, x - 1)), me = east(mc, ld1(sp, y, x + V));
+        const vec hc = ld(sq, y, x);
         vec out;
 #pragma unroll
         for (int j = 0; j < V; j++) {
           const T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
           out[j] = hc[j] + dtg * Lm;
         }
-        st(sphi, y, x, out);
+        st(sq, y, x, out);
       }
     }
     __syncthreads();
   }
-  for (int i = threadIdx.x; i < TO * TO; i += NTH) {
-    const int ty = i / TO, tx = i % TO;
+  // phi^M is in B after an odd number of substeps, else in A
+  const T *res = M % 2 == 1 ? sB : sA;
+  constexpr int NQ = TO / V;
+  for (int i = threadIdx.x; i < TO * NQ; i += NTH) {
+    const int ty = i / NQ, tx = V * (i % NQ);
     const int x = x0 + tx, y = y0 + ty;
-    if (x < p.nx && y < p.ny) phi_out[x + p.nx * y] = sphi[(H + ty) * P + OFF + H + tx];
+    if (y >= ny) continue;
+    const vec v = ld(res, H + ty, HA + tx);
+    if (whole) {
+      if (x < nx) *reinterpret_cast<vec *>(phi_out + (size_t)nx * y + x) = v;
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; j++)
+        if (x + j < nx) phi_out[(size_t)nx * y + x + j] = v[j];
+    }
   }
 }
 
@@ -1029,6 +1120,7 @@ __global__ void __launch_bounds__(TXI *TYT) k_ch_march3(KParams p, int seg, cons
   const size_t plane = (size_t)nx * ny;
   const size_t col0 = gx + (size_t)nx * gy0, col1 = gx + (size_t)nx * gy1;
   auto plane_of = [&](int t) { return wide ? wrap1(t, nz) : wrapc(t, nz); };
+  int zq = plane_of(t0 + 2);  // lattice plane of t + 2, the next refill
 
   // per row r of the pair: phi planes (t-2, t-1), h (t-3, t-2), mu (t-4, t-3),
   // u*_x, u*_y at plane t-1, u*_z planes (t-2, t-1), and the loaded plane t
@@ -1071,7 +1163,7 @@ __global__ void __launch_bounds__(TXI *TYT) k_ch_march3(KParams p, int seg, cons
       inuz[r] = quz[k][r];
     }
     if (t + 2 < t1) {  // refill the slot with plane t + 2
-      const size_t pz = plane * plane_of(t + 2);
+      const size_t pz = plane * zq;
       qphi[k][0] = phi_in[col0 + pz];
       qux[k][0] = ux_g[col0 + pz];
       quy[k][0] = uy_g[col0 + pz];
@@ -1081,6 +1173,7 @@ __global__ void __launch_bounds__(TXI *TYT) k_ch_march3(KParams p, int seg, cons
       quy[k][1] = uy_g[col1 + pz];
       quz[k][1] = uz_g[col1 + pz];
     }
+    zq = zq + 1 == nz ? 0 : zq + 1;
     __syncthreads();
     // y neighbours at the published plane: below row 0 and above row 1 from LDS,
     // between the two rows from registers
@@ -1106,17 +1199,17 @@ __global__ void __launch_bounds__(TXI *TYT) k_ch_march3(KParams p, int seg, cons
       const T uzc = uz1[r], uzd = uz2[r], uzu = inuz[r];
       T rhs;
       if constexpr (!FLUX) {
-        const T tx = pc * ((uxe - uxw) * T(0.5)) + uxc * (uxc > T(0) ? pc - pw : pe - pc);
-        const T ty_ = pc * ((uy_n - uy_s) * T(0.5)) + uyc * (uyc > T(0) ? pc - p_s : p_n - pc);
-        const T tz = pc * ((uzu - uzd) * T(0.5)) + uzc * (uzc > T(0) ? pc - pd : pu - pc);
+        const T tx = pc * ((uxe - uxw) * T(0.5)) + upwind_diff(uxc, pw, pc, pe);
+        const T ty_ = pc * ((uy_n - uy_s) * T(0.5)) + upwind_diff(uyc, p_s, pc, p_n);
+        const T tz = pc * ((uzu - uzd) * T(0.5)) + upwind_diff(uzc, pd, pc, pu);
         rhs = tx + ty_ + tz;
       } else {
         const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
         const T vyn = (uyc + uy_n) * T(0.5), vys = (uy_s + uyc) * T(0.5);
         const T vzu = (uzc + uzu) * T(0.5), vzd = (uzd + uzc) * T(0.5);
-        const T tx = (vxe > T(0) ? vxe * pc : vxe * pe) - (vxw > T(0) ? vxw * pw : vxw * pc);
-        const T ty_ = (vyn > T(0) ? vyn * pc : vyn * p_n) - (vys > T(0) ? vys * p_s : vys * pc);
-        const T tz = (vzu > T(0) ? vzu * pc : vzu * pu) - (vzd > T(0) ? vzd * pd : vzd * pc);
+        const T tx = upwind_flux(vxe, pc, pe) - upwind_flux(vxw, pw, pc);
+        const T ty_ = upwind_flux(vyn, pc, p_n) - upwind_flux(vys, p_s, pc);
+        const T tz = upwind_flux(vzu, pc, pu) - upwind_flux(vzd, pd, pc);
         rhs = tx + ty_ + tz;
       }
       hnew[r] = pc - dt * rhs;
