@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "lattice.hpp"
 
 namespace hlb {
@@ -924,6 +926,32 @@ struct RowStage {
   }
 };
 
+// Calls f(std::integral_constant<int, 0>{}) ... f(std::integral_constant<int, N - 1>{}) in order,
+// so that f can use its argument as a constant expression.
+template <class F, int... Is>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, Is...>) {
+  (f(std::integral_constant<int, Is>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// v of lane l - 1 (DIR = -1) or lane l + 1 (DIR = +1) of the wavefront, by a
+// DPP whole-wave shift; lanes 0 and 63 receive 0 for DIR = -1 and +1.
+template <int DIR, typename T>
+__device__ __forceinline__ T lane_shift(T v) {
+  constexpr int ctrl = DIR < 0 ? 0x138 : 0x130;  // wave_shr:1, wave_shl:1
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), ctrl, 0xf, 0xf, false));
+  } else {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, ctrl, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), ctrl, 0xf, 0xf, false);
+    return __builtin_bit_cast(T, (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)hi << 32));
+  }
+}
+
 // M convection-diffusion substeps of one TO x TO tile in a single launch
 // (2D, standard 5-point Laplacian).  phi and u* are staged once with a halo
 // of 3M; substep s then works on a region that shrinks by 3 on every side
@@ -934,17 +962,25 @@ struct RowStage {
 // to B, the potential overwrites phi^s in A (its phase reads phi only at
 // the site it writes) and phi^{s+1} overwrites h in B (likewise), after
 // which A and B swap roles.
-// Each thread computes V consecutive sites of a row per work item with
-// 16-byte LDS accesses; the vectors of a region are aligned down, so the
-// first and last of a row may extend past the region: those sites are
-// computed from stale values and written where nothing reads them again
-// (outside the region that the next phase reads).
+// A work item is V consecutive sites of a row (one 16-byte vector); item i
+// of a region with nq vectors per row is row i / nq, vector i % nq, and
+// thread t takes items t, t + NTH, ...  The vectors of a region are aligned
+// down, so the first and last of a row may extend past the region: those
+// sites are computed from stale values and written where nothing reads them
+// again (outside the region that the next phase reads).  The neighbour
+// west (east) of a vector's first (last) site is the last (first) element
+// of the vector in the previous (next) lane, which holds the previous (next)
+// item of the same row, except at the start (end) of a row and at the
+// edges of the wavefront: there it is read from LDS.  Every phase loop has
+// a constant trip count and is unrolled, so that one item's loads can be
+// issued under another's arithmetic.
 // NTH threads per block (256, 512 or 1024).
 template <typename T, int M, int TO, bool FLUX, int NTH>
 __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
                                                  T *__restrict__ phi_out) {
   using G = FusedTileGeom<T, M, TO>;
   constexpr int V = G::V, H = G::H, HA = G::HA, DX = G::DX, L0 = G::L0, LW = G::LW, OFF = G::OFF, P = G::PITCH;
+  static_assert(NTH % 64 == 0, "items of a wavefront are consecutive");
   typedef T vec __attribute__((ext_vector_type(V)));
   __shared__ __attribute__((aligned(16))) T sA[L0 * P], sB[L0 * P], sux[L0 * P], suy[L0 * P];
   int bx, by, bz;
@@ -967,102 +1003,113 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
   __syncthreads();
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
+  const int lane = threadIdx.x & 63;
   auto ld = [](const T *arr, int y, int x) { return *reinterpret_cast<const vec *>(arr + y * P + OFF + x); };
-  auto ld1 = [](const T *arr, int y, int x) { return arr[y * P + OFF + x]; };
   auto st = [](T *arr, int y, int x, vec v) { *reinterpret_cast<vec *>(arr + y * P + OFF + x) = v; };
-  // the V-site neighbours to the west and east of a vector c with edge values w and e
-  auto west = [](vec c, T w) {
+  // the V-site neighbours to the west and east of the vector c of item i at
+  // (y, x) of arr, in a region of nq vectors per row.  Every lane issues the
+  // LDS load (lanes served by the shift read element 0, a broadcast), so no
+  // branch is formed around it.
+  auto west = [&](const T *arr, vec c, int y, int x, int i, int nq) {
+    const bool far = i % nq == 0 || lane == 0;
+    const T l = arr[far ? y * P + OFF + x - 1 : 0];
+    const T d = lane_shift<-1>(c[V - 1]);
     vec r;
-    r[0] = w;
+    r[0] = far ? l : d;
 #pragma unroll
     for (int j = 1; j < V; j++) r[j] = c[j - 1];
     return r;
   };
-  auto east = [](vec c, T e) {
+  auto east = [&](const T *arr, vec c, int y, int x, int i, int nq) {
+    const bool far = i % nq == nq - 1 || lane == 63;
+    const T l = arr[far ? y * P + OFF + x + V : 0];
+    const T d = lane_shift<+1>(c[0]);
     vec r;
 #pragma unroll
     for (int j = 0; j < V - 1; j++) r[j] = c[j + 1];
-    r[V - 1] = e;
+    r[V - 1] = far ? l : d;
     return r;
   };
-
+  // items of a region: rows [r0, r1), columns DX + [r0, r1) widened to whole vectors
+  auto region = [](auto R0, auto R1, auto body) {
+    constexpr int r0 = decltype(R0)::value, r1 = decltype(R1)::value;
+    constexpr int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
+    constexpr int N = (r1 - r0) * nq, K = (N + NTH - 1) / NTH;
 #pragma unroll
-  for (int s = 0; s < M; s++) {
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      if (N % NTH == 0 || i < N) body(r0 + i / nq, xa + V * (i % nq), i, nq);
+    }
+  };
+  using std::integral_constant;
+
+  static_for<M>([&](auto S) {
+    constexpr int s = decltype(S)::value;
     T *const sp = s % 2 == 0 ? sA : sB;  // phi^s, then the potential
     T *const sq = s % 2 == 0 ? sB : sA;  // h, then phi^{s+1}
-    const int lo = 3 * s;
-    // h on rows [lo + 1, L0 - lo - 1), columns DX + the same range
-    {
-      const int r0 = lo + 1, r1 = L0 - lo - 1;
-      const int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
-      for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
-        const int y = r0 + i / nq, x = xa + V * (i % nq);
-        const vec pc = ld(sp, y, x), pdn = ld(sp, y - 1, x), pup = ld(sp, y + 1, x);
-        const vec pw = west(pc, ld1(sp, y, x - 1)), pe = east(pc, ld1(sp, y, x + V));
-        const vec uxc = ld(sux, y, x);
-        const vec uxw = west(uxc, ld1(sux, y, x - 1)), uxe = east(uxc, ld1(sux, y, x + V));
-        const vec uyc = ld(suy, y, x), uyd = ld(suy, y - 1, x), uyu = ld(suy, y + 1, x);
-        vec h;
+    constexpr int lo = 3 * s;
+    // h on rows [lo + 1, L0 - lo - 1)
+    region(integral_constant<int, lo + 1>{}, integral_constant<int, L0 - lo - 1>{},
+           [&](int y, int x, int i, int nq) {
+             const vec pc = ld(sp, y, x), pdn = ld(sp, y - 1, x), pup = ld(sp, y + 1, x);
+             const vec uxc = ld(sux, y, x);
+             const vec uyc = ld(suy, y, x), uyd = ld(suy, y - 1, x), uyu = ld(suy, y + 1, x);
+             const vec pw = west(sp, pc, y, x, i, nq), pe = east(sp, pc, y, x, i, nq);
+             const vec uxw = west(sux, uxc, y, x, i, nq), uxe = east(sux, uxc, y, x, i, nq);
+             vec h;
 #pragma unroll
-        for (int j = 0; j < V; j++) {
-          T rhs;
-          if constexpr (!FLUX) {
-            const T tx = pc[j] * ((uxe[j] - uxw[j]) * T(0.5)) + uxc[j] * (uxc[j] > T(0) ? pc[j] - pw[j] : pe[j] - pc[j]);
-            const T ty =
-                pc[j] * ((uyu[j] - uyd[j]) * T(0.5)) + uyc[j] * (uyc[j] > T(0) ? pc[j] - pdn[j] : pup[j] - pc[j]);
-            rhs = tx + ty;
-          } else {
-            const T vxe = (uxc[j] + uxe[j]) * T(0.5), vxw = (uxw[j] + uxc[j]) * T(0.5);
-            const T vyu = (uyc[j] + uyu[j]) * T(0.5), vyd = (uyd[j] + uyc[j]) * T(0.5);
-            const T tx = (vxe > T(0) ? vxe * pc[j] : vxe * pe[j]) - (vxw > T(0) ? vxw * pw[j] : vxw * pc[j]);
-            const T ty = (vyu > T(0) ? vyu * pc[j] : vyu * pup[j]) - (vyd > T(0) ? vyd * pdn[j] : vyd * pc[j]);
-            rhs = tx + ty;
-          }
-          h[j] = pc[j] - dt * rhs;
-        }
-        st(sq, y, x, h);
-      }
-    }
+             for (int j = 0; j < V; j++) {
+               T rhs;
+               if constexpr (!FLUX) {
+                 const T tx =
+                     pc[j] * ((uxe[j] - uxw[j]) * T(0.5)) + uxc[j] * (uxc[j] > T(0) ? pc[j] - pw[j] : pe[j] - pc[j]);
+                 const T ty = pc[j] * ((uyu[j] - uyd[j]) * T(0.5)) +
+                              uyc[j] * (uyc[j] > T(0) ? pc[j] - pdn[j] : pup[j] - pc[j]);
+                 rhs = tx + ty;
+               } else {
+                 const T vxe = (uxc[j] + uxe[j]) * T(0.5), vxw = (uxw[j] + uxc[j]) * T(0.5);
+                 const T vyu = (uyc[j] + uyu[j]) * T(0.5), vyd = (uyd[j] + uyc[j]) * T(0.5);
+                 const T tx = (vxe > T(0) ? vxe * pc[j] : vxe * pe[j]) - (vxw > T(0) ? vxw * pw[j] : vxw * pc[j]);
+                 const T ty =
+                     (vyu > T(0) ? vyu * pc[j] : vyu * pup[j]) - (vyd > T(0) ? vyd * pdn[j] : vyd * pc[j]);
+                 rhs = tx + ty;
+               }
+               h[j] = pc[j] - dt * rhs;
+             }
+             st(sq, y, x, h);
+           });
     __syncthreads();
     // diffusion potential on [lo + 2, L0 - lo - 2), over phi^s
-    {
-      const int r0 = lo + 2, r1 = L0 - lo - 2;
-      const int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
-      for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
-        const int y = r0 + i / nq, x = xa + V * (i % nq);
-        const vec hc = ld(sq, y, x), hdn = ld(sq, y - 1, x), hup = ld(sq, y + 1, x);
-        const vec hw = west(hc, ld1(sq, y, x - 1)), he = east(hc, ld1(sq, y, x + V));
-        const vec ph = ld(sp, y, x);
-        vec mu;
+    region(integral_constant<int, lo + 2>{}, integral_constant<int, L0 - lo - 2>{},
+           [&](int y, int x, int i, int nq) {
+             const vec hc = ld(sq, y, x), hdn = ld(sq, y - 1, x), hup = ld(sq, y + 1, x);
+             const vec ph = ld(sp, y, x);
+             const vec hw = west(sq, hc, y, x, i, nq), he = east(sq, hc, y, x, i, nq);
+             vec mu;
 #pragma unroll
-        for (int j = 0; j < V; j++) {
-          const T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
-          mu[j] = a * hc[j] + b * ph[j] * ph[j] * ph[j] - kappa * Lh;
-        }
-        st(sp, y, x, mu);
-      }
-    }
+             for (int j = 0; j < V; j++) {
+               const T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
+               mu[j] = a * hc[j] + b * ph[j] * ph[j] * ph[j] - kappa * Lh;
+             }
+             st(sp, y, x, mu);
+           });
     __syncthreads();
     // phi^{s+1} on [lo + 3, L0 - lo - 3), over h
-    {
-      const int r0 = lo + 3, r1 = L0 - lo - 3;
-      const int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
-      for (int i = threadIdx.x; i < (r1 - r0) * nq; i += NTH) {
-        const int y = r0 + i / nq, x = xa + V * (i % nq);
-        const vec mc = ld(sp, y, x), mdn = ld(sp, y - 1, x), mup = ld(sp, y + 1, x);
-        const vec mw = west(mc, ld1(sp, y, x - 1)), me = east(mc, ld1(sp, y, x + V));
-        const vec hc = ld(sq, y, x);
-        vec out;
+    region(integral_constant<int, lo + 3>{}, integral_constant<int, L0 - lo - 3>{},
+           [&](int y, int x, int i, int nq) {
+             const vec mc = ld(sp, y, x), mdn = ld(sp, y - 1, x), mup = ld(sp, y + 1, x);
+             const vec hc = ld(sq, y, x);
+             const vec mw = west(sp, mc, y, x, i, nq), me = east(sp, mc, y, x, i, nq);
+             vec out;
 #pragma unroll
-        for (int j = 0; j < V; j++) {
-          const T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
-          out[j] = hc[j] + dtg * Lm;
-        }
-        st(sq, y, x, out);
-      }
-    }
+             for (int j = 0; j < V; j++) {
+               const T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
+               out[j] = hc[j] + dtg * Lm;
+             }
+             st(sq, y, x, out);
+           });
     __syncthreads();
-  }
+  });
   // phi^M is in B after an odd number of substeps, else in A
   const T *res = M % 2 == 1 ? sB : sA;
   constexpr int NQ = TO / V;
