@@ -41,6 +41,11 @@ WORKLOADS = {
                           "D2Q9 drop R=20 128x128 periodic, FP64"),
     "d3q19_spinodal_256": ((256, 256, 256), "f32", dict(BASE, N=1 / 6, Q=1 / 3),
                            "D3Q19 spinodal 256^3 periodic, FP32 shifted populations"),
+    # the same with the isotropic 19-point convection-diffusion Laplacian
+    # (Q = 1/3, R = 1/6), whose smaller largest eigenvalue allows m = 3
+    "d3q19_spinodal_256_iso": ((256, 256, 256), "f32", dict(BASE, N=1 / 6, Q=1 / 3, cd_Q=1 / 3),
+                               "D3Q19 spinodal 256^3 periodic, isotropic CH Laplacian (m = 3), "
+                               "FP32 shifted populations"),
     # shape None: a batch of independent simulations (batch_workload)
     "d2q9_batch_512": (None, "f32", dict(BASE, **PAPER_STENCIL),
                        "512 independent D2Q9 drop/slab simulations, L ~ U{64..256}, kappa ~ U(0.05, 0.2), "

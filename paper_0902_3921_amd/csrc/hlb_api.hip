@@ -353,15 +353,24 @@ struct Ops {
   }
   // one fused launch of M substeps: phi[phicur] -> phi[1 - phicur]
   // TXI x TYT threads, two y rows each: output (TXI - 6) x (2 TYT - 6) columns per block
+  // (the 7-point Laplacian for cd_Q = 1, else the 19-point one)
   template <int TXI, int TYT>
   static void march3_1(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
     const dim3 grid(ceil_div(c->nx, TXI - 6), ceil_div(c->ny, 2 * TYT - 6), ceil_div(c->nz, c->plan.seg));
-    if (k.advection == 1)
-      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYT, true>), grid, dim3(TXI * TYT), 0, c->stream, k, c->plan.seg,
-                         src, at<T>(c, c->lay.u), dst);
-    else
-      hipLaunchKernelGGL((k_ch_march3<T, TXI, TYT, false>), grid, dim3(TXI * TYT), 0, c->stream, k, c->plan.seg,
-                         src, at<T>(c, c->lay.u), dst);
+    const dim3 blk(TXI * TYT);
+    const int seg = c->plan.seg;
+    const T *uu = at<T>(c, c->lay.u);
+    if (c->p.cd_Q == 1.0) {
+      if (k.advection == 1)
+        hipLaunchKernelGGL((k_ch_march3<T, TXI, TYT, true>), grid, blk, 0, c->stream, k, seg, src, uu, dst);
+      else
+        hipLaunchKernelGGL((k_ch_march3<T, TXI, TYT, false>), grid, blk, 0, c->stream, k, seg, src, uu, dst);
+    } else if constexpr (TXI * TYT <= 512) {  // plan_valid keeps the 19-point march to 512 threads
+      if (k.advection == 1)
+        hipLaunchKernelGGL((k_ch_march3w<T, TXI, TYT, true>), grid, blk, 0, c->stream, k, seg, src, uu, dst);
+      else
+        hipLaunchKernelGGL((k_ch_march3w<T, TXI, TYT, false>), grid, blk, 0, c->stream, k, seg, src, uu, dst);
+    }
   }
   static void march(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
     if constexpr (L::D == 3) {
@@ -564,8 +573,8 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
     *why = "plan kind must be 0, 1 or 2";
     return false;
   }
-  if (c->p.cd_Q != 1.0) {
-    *why = "the marching substep kernels need cd_Q = 1";
+  if (c->lattice == HLB_D2Q9 && c->p.cd_Q != 1.0) {
+    *why = "the 2D marching substep kernels need cd_Q = 1";
     return false;
   }
   if (c->lattice == HLB_D3Q19) {
@@ -580,6 +589,10 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
     }
     if (c->storage == HLB_F64 && pl.bw == 1024) {
       *why = "3D double storage needs bw <= 512 (LDS size)";
+      return false;
+    }
+    if (c->p.cd_Q != 1.0 && pl.bw == 1024) {
+      *why = "the 3D march with the 19-point Laplacian needs bw <= 512 (registers)";
       return false;
     }
     if (pl.seg < 1) {
@@ -1029,8 +1042,8 @@ const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
     hlb_ctx *mc = const_cast<hlb_ctx *>(c);
     char buf[160];
     if (c->lattice == HLB_D3Q19)
-      snprintf(buf, sizeof buf, "hlb::k_ch_march3<%s, %d threads>", c->storage == HLB_F64 ? "double" : "float",
-               c->plan.bw);
+      snprintf(buf, sizeof buf, "hlb::%s<%s, %d threads>", c->p.cd_Q == 1.0 ? "k_ch_march3" : "k_ch_march3w",
+               c->storage == HLB_F64 ? "double" : "float", c->plan.bw);
     else
       snprintf(buf, sizeof buf, "hlb::k_ch_march<%s, %d, %d>", c->storage == HLB_F64 ? "double" : "float",
                std::min(c->plan.fuse, c->m), c->plan.bw);
@@ -1067,7 +1080,7 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   // current phi and writing scratch buffers, so the state is unchanged
   std::vector<ChPlan> cand;
   cand.push_back(ChPlan{0, 1, 128, 64});
-  if (c->lattice == HLB_D3Q19 && c->p.cd_Q == 1.0) {
+  if (c->lattice == HLB_D3Q19) {
     for (int bw : {256, 512, 1024}) {
       std::vector<int> segs = {8, 16, 32, 64, 128};
       // segment heights that make the block count just reach a multiple of

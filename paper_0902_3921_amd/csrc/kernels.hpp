@@ -1295,6 +1295,207 @@ __global__ void __launch_bounds__(TXI *TYT) k_ch_march3(KParams p, int seg, cons
   }
 }
 
+// One convection-diffusion substep in 3D with the general 19-point Laplacian
+// of the C14 form (weight cQ on the 6 faces, cR on the 12 edges, cC at the
+// centre; cd_Q != 1), marching along z with the thread layout of
+// k_ch_march3.  The Laplacian of a plane needs the in-plane neighbours of
+// the planes above and below it, so the pipeline lags further: iteration t
+// (input plane t) forms h at plane t-1 by the advection half-step, the
+// diffusion potential at plane t-3 from h on planes t-4 .. t-2, and phi' at
+// plane t-5 from the potential on planes t-6 .. t-4.  Every plane those two
+// Laplacians read was formed in an earlier iteration: h and the potential
+// are published into rings of four LDS planes (an iteration reads the two
+// newest, the next one overwrites the oldest), so one barrier per plane
+// still suffices.  With F(p) the sum over the 4 in-plane face neighbours
+// and E(p) over the 4 in-plane diagonal neighbours of a column on plane p,
+//   L q(p) = cQ [F(p) + q(p-1) + q(p+1)] + cR [E(p) + F(p-1) + F(p+1)] + cC q(p),
+// so F of each plane is formed once, when the plane is newest, and kept in
+// registers for the two later Laplacians that use it.
+template <typename T, int TXI, int TYT, bool FLUX>
+__global__ void __launch_bounds__(TXI *TYT) k_ch_march3w(KParams p, int seg, const T *__restrict__ phi_in,
+                                                         const T *__restrict__ u, T *__restrict__ phi_out) {
+  constexpr int TYI = 2 * TYT;
+  __shared__ T xphi[2][TYI][TXI], xux[2][TYI][TXI], xuy[2][TYI][TXI], rh[4][TYI][TXI], rm[4][TYI][TXI];
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const int cx = threadIdx.x % TXI, ty = threadIdx.x / TXI;
+  const int cy0 = 2 * ty, cy1 = 2 * ty + 1;
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int X0 = bx * (TXI - 6), Y0 = by * (TYI - 6);
+  const int z0 = bz * seg, z1 = min(z0 + seg, nz);
+  const int gx = wrapc(X0 - 3 + cx, nx);
+  const int gy0 = wrapc(Y0 - 3 + cy0, ny), gy1 = wrapc(Y0 - 3 + cy1, ny);
+  const bool xin = cx >= 3 && cx < TXI - 3 && X0 + cx - 3 < nx;
+  const bool out0 = xin && cy0 >= 3 && cy0 < TYI - 3 && Y0 + cy0 - 3 < ny;
+  const bool out1 = xin && cy1 >= 3 && cy1 < TYI - 3 && Y0 + cy1 - 3 < ny;
+  // edge lanes read themselves; their results are never used
+  const int cxm = cx > 0 ? cx - 1 : 0, cxp = cx < TXI - 1 ? cx + 1 : TXI - 1;
+  const int cym = cy0 > 0 ? cy0 - 1 : 0, cyp = cy1 < TYI - 1 ? cy1 + 1 : TYI - 1;
+  const size_t ns = (size_t)p.ns;
+  const T *ux_g = u, *uy_g = u + ns, *uz_g = u + 2 * ns;
+  const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
+  const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cR = T(p.cR), cC = T(p.cC);
+  const int t0 = z0 - 3, t1 = z1 + 5;  // iterations [t0, t1); output plane t - 5
+  const bool wide = nz >= 4;
+  const size_t plane = (size_t)nx * ny;
+  const size_t col0 = gx + (size_t)nx * gy0, col1 = gx + (size_t)nx * gy1;
+  auto plane_of = [&](int t) { return wide ? wrap1(t, nz) : wrapc(t, nz); };
+  int zq = plane_of(t0 + 2);  // lattice plane of t + 2, the next refill
+
+  // per row r of the pair: phi planes t-1, t-2, t-3; u*_x, u*_y at t-1; u*_z
+  // at t-2, t-1; h at t-2 .. t-5 and F_h at t-3, t-4; the potential at
+  // t-4 .. t-6 and F_mu at t-5, t-6
+  T ph1[2] = {0, 0}, ph2[2] = {0, 0}, ph3[2] = {0, 0};
+  T ux1[2] = {0, 0}, uy1[2] = {0, 0}, uz2[2] = {0, 0}, uz1[2] = {0, 0};
+  T h2[2] = {0, 0}, h3[2] = {0, 0}, h4[2] = {0, 0}, h5[2] = {0, 0}, fh3[2] = {0, 0}, fh4[2] = {0, 0};
+  T m4[2] = {0, 0}, m5[2] = {0, 0}, m6[2] = {0, 0}, fm5[2] = {0, 0}, fm6[2] = {0, 0};
+  // input planes in flight: queue slot k holds plane t0 + k + 2j at its j-th use
+  T qphi[2][2], qux[2][2], quy[2][2], quz[2][2];
+#pragma unroll
+  for (int k = 0; k < 2; k++) {
+    if (t0 + k < t1) {
+      const size_t pz = plane * plane_of(t0 + k);
+      qphi[k][0] = phi_in[col0 + pz];
+      qux[k][0] = ux_g[col0 + pz];
+      quy[k][0] = uy_g[col0 + pz];
+      quz[k][0] = uz_g[col0 + pz];
+      qphi[k][1] = phi_in[col1 + pz];
+      qux[k][1] = ux_g[col1 + pz];
+      quy[k][1] = uy_g[col1 + pz];
+      quz[k][1] = uz_g[col1 + pz];
+    }
+  }
+  // in-plane face sum and diagonal sum of a ring plane at both rows of the
+  // pair; q0, q1 are this thread's own values of that plane
+  auto face = [&](const T (&r)[TYI][TXI], const T q0, const T q1, T f[2]) {
+    f[0] = (r[cy0][cxp] + r[cy0][cxm]) + (q1 + r[cym][cx]);
+    f[1] = (r[cy1][cxp] + r[cy1][cxm]) + (r[cyp][cx] + q0);
+  };
+  auto diag = [&](const T (&r)[TYI][TXI], T e[2]) {
+    const T s_m = r[cym][cxp] + r[cym][cxm], s_0 = r[cy0][cxp] + r[cy0][cxm];
+    const T s_1 = r[cy1][cxp] + r[cy1][cxm], s_p = r[cyp][cxp] + r[cyp][cxm];
+    e[0] = s_1 + s_m;
+    e[1] = s_p + s_0;
+  };
+  // one iteration: input plane t from queue slot k (parity of the published planes = k)
+  auto iterate = [&](const int t, const int k) {
+    const int par = k;
+    const int cy[2] = {cy0, cy1};
+    const int sh = (t - 2) & 3, shp = (t - 3) & 3;  // ring planes of h at t-2, t-3
+    const int sm = (t - 4) & 3, smp = (t - 5) & 3;  // ring planes of mu at t-4, t-5
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      xphi[par][cy[r]][cx] = ph1[r];
+      xux[par][cy[r]][cx] = ux1[r];
+      xuy[par][cy[r]][cx] = uy1[r];
+      rh[sh][cy[r]][cx] = h2[r];
+      rm[sm][cy[r]][cx] = m4[r];
+    }
+    T in[2], inux[2], inuy[2], inuz[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      in[r] = qphi[k][r];
+      inux[r] = qux[k][r];
+      inuy[r] = quy[k][r];
+      inuz[r] = quz[k][r];
+    }
+    if (t + 2 < t1) {  // refill the slot with plane t + 2
+      const size_t pz = plane * zq;
+      qphi[k][0] = phi_in[col0 + pz];
+      qux[k][0] = ux_g[col0 + pz];
+      quy[k][0] = uy_g[col0 + pz];
+      quz[k][0] = uz_g[col0 + pz];
+      qphi[k][1] = phi_in[col1 + pz];
+      qux[k][1] = ux_g[col1 + pz];
+      quy[k][1] = uy_g[col1 + pz];
+      quz[k][1] = uz_g[col1 + pz];
+    }
+    zq = zq + 1 == nz ? 0 : zq + 1;
+    __syncthreads();
+    // advection half-step at plane t-1 (face neighbours only)
+    const T phs = xphi[par][cym][cx], phn = xphi[par][cyp][cx];
+    const T uys = xuy[par][cym][cx], uyn = xuy[par][cyp][cx];
+    T hnew[2];
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const int y = cy[r];
+      const T p_s = r == 0 ? phs : ph1[0], p_n = r == 0 ? ph1[1] : phn;
+      const T uy_s = r == 0 ? uys : uy1[0], uy_n = r == 0 ? uy1[1] : uyn;
+      const T pc = ph1[r];
+      const T pw = xphi[par][y][cxm], pe = xphi[par][y][cxp];
+      const T pd = ph2[r], pu = in[r];
+      const T uxc = ux1[r], uxw = xux[par][y][cxm], uxe = xux[par][y][cxp];
+      const T uyc = uy1[r];
+      const T uzc = uz1[r], uzd = uz2[r], uzu = inuz[r];
+      T rhs;
+      if constexpr (!FLUX) {
+        const T tx = pc * ((uxe - uxw) * T(0.5)) + upwind_diff(uxc, pw, pc, pe);
+        const T ty_ = pc * ((uy_n - uy_s) * T(0.5)) + upwind_diff(uyc, p_s, pc, p_n);
+        const T tz = pc * ((uzu - uzd) * T(0.5)) + upwind_diff(uzc, pd, pc, pu);
+        rhs = tx + ty_ + tz;
+      } else {
+        const T vxe = (uxc + uxe) * T(0.5), vxw = (uxw + uxc) * T(0.5);
+        const T vyn = (uyc + uy_n) * T(0.5), vys = (uy_s + uyc) * T(0.5);
+        const T vzu = (uzc + uzu) * T(0.5), vzd = (uzd + uzc) * T(0.5);
+        const T tx = upwind_flux(vxe, pc, pe) - upwind_flux(vxw, pw, pc);
+        const T ty_ = upwind_flux(vyn, pc, p_n) - upwind_flux(vys, p_s, pc);
+        const T tz = upwind_flux(vzu, pc, pu) - upwind_flux(vzd, pd, pc);
+        rhs = tx + ty_ + tz;
+      }
+      hnew[r] = pc - dt * rhs;
+    }
+    // the potential at plane t-3 from h on planes t-4 .. t-2
+    T fh2[2], eh3[2], mnew[2];
+    face(rh[sh], h2[0], h2[1], fh2);
+    diag(rh[shp], eh3);
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const T Lh = cQ * (fh3[r] + (h2[r] + h4[r])) + cR * (eh3[r] + (fh2[r] + fh4[r])) + cC * h3[r];
+      mnew[r] = a * h3[r] + b * ph3[r] * ph3[r] * ph3[r] - kappa * Lh;
+    }
+    // phi' at plane t-5 from the potential on planes t-6 .. t-4
+    T fm4[2], em5[2], out[2];
+    face(rm[sm], m4[0], m4[1], fm4);
+    diag(rm[smp], em5);
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      const T Lm = cQ * (fm5[r] + (m4[r] + m6[r])) + cR * (em5[r] + (fm4[r] + fm6[r])) + cC * m5[r];
+      out[r] = h5[r] + dtg * Lm;
+    }
+#pragma unroll
+    for (int r = 0; r < 2; r++) {
+      ph3[r] = ph2[r];
+      ph2[r] = ph1[r];
+      ph1[r] = in[r];
+      ux1[r] = inux[r];
+      uy1[r] = inuy[r];
+      uz2[r] = uz1[r];
+      uz1[r] = inuz[r];
+      h5[r] = h4[r];
+      h4[r] = h3[r];
+      h3[r] = h2[r];
+      h2[r] = hnew[r];
+      fh4[r] = fh3[r];
+      fh3[r] = fh2[r];
+      m6[r] = m5[r];
+      m5[r] = m4[r];
+      m4[r] = mnew[r];
+      fm6[r] = fm5[r];
+      fm5[r] = fm4[r];
+    }
+    const int zo = t - 5;
+    if (zo >= z0 && zo < z1) {
+      if (out0) phi_out[col0 + plane * zo] = out[0];
+      if (out1) phi_out[col1 + plane * zo] = out[1];
+    }
+  };
+  // unrolled by two so the queue slot and the parity are static
+  for (int t = t0; t < t1; t += 2) {
+    iterate(t, 0);
+    if (t + 1 < t1) iterate(t + 1, 1);
+  }
+}
+
 // f_i = f_i^eq(n0, u0) (Eq. espdistrfunc) from double-precision inputs
 // io = [phi | n | u (d components)]; stored pull-wise, g_i(r) = f_i(r + e_i) - w_i rho0.
 template <class L, typename T>

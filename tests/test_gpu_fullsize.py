@@ -31,6 +31,7 @@ def hlb():
     ("d2q9_spinodal_1024", 20, "standard"),
     ("d2q9_spinodal_4096", 4, None),
     ("d3q19_spinodal_256", 2, None),
+    ("d3q19_spinodal_256_iso", 2, None),
 ])
 def test_benchmark_workload_full_size(hlb, name, steps, stencil):
     import bench

@@ -319,6 +319,10 @@ def test_invalid_plans_rejected(hlb):
     g3d = hlb.Sim((8, 8, 8), "f64", **BASE)
     with pytest.raises(hlb.HlbError):
         g3d.set_plan(1, 1, 1024, 8)
+    g3w = hlb.Sim((8, 8, 8), "f32", **BASE, cd_Q=1 / 3)
+    g3w.set_plan(1, 1, 512, 8)
+    with pytest.raises(hlb.HlbError):
+        g3w.set_plan(1, 1, 1024, 8)
     g2 = hlb.Sim((32, 32), "f32", **BASE, cd_Q=2 / 3)
     assert g2.plan[0] == 0
     with pytest.raises(hlb.HlbError):
@@ -345,17 +349,21 @@ def test_autotune_keeps_state_and_parity(hlb):
 @pytest.mark.parametrize("plan", [(0, 1, 128, 64), (1, 1, 256, 5), (1, 1, 512, 7), (1, 1, 1024, 16)])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 @pytest.mark.parametrize("advection", [0, 1])
-def test_d3q19_substep_plans_agree(hlb, plan, storage, advection):
-    """The 3D z-marching substep kernel (block shapes 16x16, 32x16, 64x16,
-    various segment heights) and the tiled kernel give the oracle's step on
-    a ragged 70 x 37 x 21 lattice."""
+@pytest.mark.parametrize("cd_Q", [1.0, 1 / 3], ids=["lap7", "lap19"])
+def test_d3q19_substep_plans_agree(hlb, plan, storage, advection, cd_Q):
+    """The 3D z-marching substep kernels (block shapes 16x16, 32x16, 64x16,
+    various segment heights; the 7-point convection-diffusion Laplacian,
+    m = 10, and the isotropic 19-point one, m = 3) and the tiled kernel give
+    the oracle's step on a ragged 70 x 37 x 21 lattice."""
     if storage == "f64" and plan[2] > 512:
         pytest.skip("bw = 1024 needs float storage")
+    if cd_Q != 1.0 and plan[2] > 512:
+        pytest.skip("the 19-point march takes at most 512 threads (registers)")
     shape = (21, 37, 70)
     phi = _drop(shape, 8, BASE) + synth.spinodal(shape, seed=9, amp=0.02)
     u0 = np.zeros((3,) + shape)
     u0[0], u0[1], u0[2] = 0.004, -0.006, 0.005
-    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=1 / 6, Q=1 / 3, advection=advection)
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=1 / 6, Q=1 / 3, advection=advection, cd_Q=cd_Q)
     gpu.set_plan(*plan)
     gpu.step(4)
     ora.step(4)
@@ -364,12 +372,13 @@ def test_d3q19_substep_plans_agree(hlb, plan, storage, advection):
     assert max(d.values()) < tol, (plan, d)
 
 
-def test_d3q19_march_thin_lattices(hlb):
+@pytest.mark.parametrize("cd_Q", [1.0, 1 / 3], ids=["lap7", "lap19"])
+def test_d3q19_march_thin_lattices(hlb, cd_Q):
     """z-marching with fewer planes than its halo, and x-y tiles wider than
     the lattice (periodic images)."""
     for shape in [(3, 12, 40), (9, 5, 6), (1, 8, 8)]:
         phi = synth.spinodal(shape, seed=sum(shape), amp=0.3)
-        gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=1 / 6, Q=1 / 3)
+        gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=1 / 6, Q=1 / 3, cd_Q=cd_Q)
         gpu.set_plan(1, 1, 256, 2)
         gpu.step(3)
         ora.step(3)
