@@ -98,10 +98,12 @@ def test_drop_workload_conservation_and_spurious_velocity(hlb, storage):
     assert r1["umax"] < 1e-2
 
 
-def test_laplace_law_3d(hlb):
+@pytest.mark.parametrize("cd_Q,m", [(1.0, 10), (1 / 3, 3)], ids=["lap7", "lap19"])
+def test_laplace_law_3d(hlb, cd_Q, m):
     """D3Q19: relaxed spherical drops of radii 12, 14, 16 in 64^3 (FP32, the
-    3D workload's stencil N = 1/6, Q = 1/3, mu-first force, m = 10, 6000
-    steps):
+    3D workload's stencil N = 1/6, Q = 1/3, mu-first force, 6000 steps; the
+    7-point convection-diffusion Laplacian with m = 10 and the isotropic
+    19-point one with m = 3):
     Delta p = 2 sigma / R with the 2D sigma of Eq. surftens (the planar
     interface tension does not depend on the dimension), fit through the
     origin within 8%, every drop within 12%; R is the equivalent-volume
@@ -112,8 +114,9 @@ def test_laplace_law_3d(hlb):
     L, c = 64, 32
     inv_r, dp = [], []
     for R in (12, 14, 16):
-        sim = hlb.Sim((L, L, L), "f32", **BASE, N=1 / 6, Q=1 / 3, force_form=0)
-        assert sim.m == 10
+        sim = hlb.Sim((L, L, L), "f32", **BASE, N=1 / 6, Q=1 / 3, force_form=0, cd_Q=cd_Q)
+        assert sim.m == m
+        sim.set_plan(1, 1, 512, 16)  # the z-march of this Laplacian
         sim.init(synth.drop((L, L, L), R, 1.0, _w(a, kappa)))
         sim.step(6000)
         f = sim.fields()
@@ -124,7 +127,7 @@ def test_laplace_law_3d(hlb):
         sim.close()
     inv_r, dp = np.array(inv_r), np.array(dp)
     slope = (dp * inv_r).sum() / (inv_r ** 2).sum()
-    print(f"3D: 2 sigma fit {slope:.5e}, Eq. surftens x 2 = {2 * sigma:.5e}, per drop "
+    print(f"3D cd_Q = {cd_Q:.3f}: 2 sigma fit {slope:.5e}, Eq. surftens x 2 = {2 * sigma:.5e}, per drop "
           f"{np.round(dp / (2 * sigma * inv_r), 4)}", flush=True)
     assert abs(slope / (2 * sigma) - 1) < 0.08
     assert np.all(np.abs(dp / (2 * sigma * inv_r) - 1) < 0.12)
