@@ -427,7 +427,7 @@ def main():
                     help="also run a device copy of this many MiB (for the HBM counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU domain decomposition is design only)", file=sys.stderr)
         sys.exit(2)
 
