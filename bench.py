@@ -151,6 +151,15 @@ def run_gpu(name, steps, warmup, plan=None):
     sim.close()
     sim_sc, secs_sc, _ = timed(dict(kw, **STANDARD_STENCIL), plan)
     sim_sc.close()
+    # the scheme variants of the method, each with its own autotuned plan
+    variants = {}
+    var_params = {"flux_advection": dict(kw, advection=1), "mu_first_force": dict(kw, force_form=0)}
+    if kw.get("cd_Q", 1.0) == 1.0:
+        var_params["isotropic_ch_laplacian"] = dict(kw, cd_Q=2 / 3 if d == 2 else 1 / 3)
+    for vname, vkw in var_params.items():
+        vsim, vsecs, _ = timed(vkw)
+        variants[vname] = {"mlups": ns * steps / vsecs / 1e6, "m": vsim.m, "substep_plan": list(vsim.plan)}
+        vsim.close()
 
     lb_b, ch_b, step_b = algorithmic_bytes(d, q, es)
     t_lb = ms_lb / nprof * 1e-3            # s per launch
@@ -172,7 +181,8 @@ def run_gpu(name, steps, warmup, plan=None):
     mlups = ns * steps / secs / 1e6
     return {
         "shape": shape, "storage": storage, "desc": desc, "m": m, "ns": ns, "secs": secs,
-        "mlups": mlups, "mlups_standard": ns * steps / secs_sc / 1e6, "stats": stats, "plan": plan,
+        "mlups": mlups, "mlups_standard": ns * steps / secs_sc / 1e6, "variants": variants, "stats": stats,
+        "plan": plan,
         "host_io": {"init_ms": t_init * 1e3, "get_fields_ms": t_fields * 1e3,
                     "pcie_inclusive_mlups": ns * steps / (secs + t_init + t_fields) / 1e6},
         "kernels": {"lb": {"name": names[0], "us_per_launch": t_lb * 1e6, "bytes_per_lu": lb_b,
@@ -488,6 +498,7 @@ def main():
                      "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": kd["gbs"] / copy_gbs},
         "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
         "mlups_standard_stencil": r["mlups_standard"],
+        "variants": r.get("variants"),
         "host_io": r.get("host_io"),
         "kernels": r["kernels"],
         "check": {k: r["stats"][k] for k in ("finite", "mass", "umax", "umax_sim") if k in r["stats"]},
