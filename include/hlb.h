@@ -176,10 +176,11 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
 /* Execution plan of the convection-diffusion substeps (a performance
  * choice; every plan computes the same values up to rounding order):
  *   plan[0] kind: 0 = one tiled launch per substep (any lattice, any cd_Q);
- *                 1 = marching launches (cd_Q = 1 only): in D2Q9 a launch
- *                     marches along y and runs plan[1] substeps; in D3Q19 a
- *                     launch marches along z and runs one substep;
- *                 2 = fused tiles (D2Q9, cd_Q = 1): a launch runs plan[1]
+ *                 1 = marching launches: in D2Q9 (cd_Q = 1 only) a launch
+ *                     marches along y and runs plan[1] substeps; in D3Q19
+ *                     (any cd_Q) a launch marches along z and runs one
+ *                     substep;
+ *                 2 = fused tiles (D2Q9, any cd_Q): a launch runs plan[1]
  *                     substeps (1, 2, 3 or 5) of plan[2] x plan[2] tiles
  *                     (16, 32, 48 or 64) in LDS, halo 3 per substep, when the
  *                     staged tile fits a CU's 160 KiB of LDS;
@@ -188,7 +189,7 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
  *                 HLB_F32_SHIFTED only), bw - 6*fuse >= 16;
  *                 D3Q19: threads per block, each owning two (x, y)
  *                 columns: 256 (16x32 columns), 512 (32x32) or 1024 (64x32,
- *                 HLB_F32_SHIFTED only);
+ *                 HLB_F32_SHIFTED and cd_Q = 1 only);
  *   plan[3] seg:  kind 1: rows (D2Q9) or planes (D3Q19) per block, >= 1;
  *                 kind 2: threads per block, 256, 512 or 1024 (0 = 256).
  * hlb_create picks a plan from the lattice size; hlb_set_plan overrides it

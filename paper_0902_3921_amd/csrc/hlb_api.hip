@@ -393,12 +393,17 @@ struct Ops {
     static_assert(fused_tile_lds(sizeof(T), M, TO) == FusedTileGeom<T, M, TO>::LDS, "LDS formula");
     if constexpr (fused_tile_lds(sizeof(T), M, TO) <= kMaxLds) {
       const dim3 grid(ceil_div(c->nx, TO), ceil_div(c->ny, TO));
-      if (k.advection == 1)
-        hipLaunchKernelGGL((k_ch_tile<T, M, TO, true, NTH>), grid, dim3(NTH), 0, c->stream, k, src,
-                           at<T>(c, c->lay.u), dst);
+      const T *uu = at<T>(c, c->lay.u);
+      const bool lap9 = c->p.cd_Q != 1.0;
+      if (k.advection == 1 && lap9)
+        hipLaunchKernelGGL((k_ch_tile<T, M, TO, true, NTH, true>), grid, dim3(NTH), 0, c->stream, k, src, uu, dst);
+      else if (k.advection == 1)
+        hipLaunchKernelGGL((k_ch_tile<T, M, TO, true, NTH, false>), grid, dim3(NTH), 0, c->stream, k, src, uu, dst);
+      else if (lap9)
+        hipLaunchKernelGGL((k_ch_tile<T, M, TO, false, NTH, true>), grid, dim3(NTH), 0, c->stream, k, src, uu, dst);
       else
-        hipLaunchKernelGGL((k_ch_tile<T, M, TO, false, NTH>), grid, dim3(NTH), 0, c->stream, k, src,
-                           at<T>(c, c->lay.u), dst);
+        hipLaunchKernelGGL((k_ch_tile<T, M, TO, false, NTH, false>), grid, dim3(NTH), 0, c->stream, k, src, uu,
+                           dst);
     }
   }
   template <int M, int TO>
@@ -547,8 +552,8 @@ void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
 bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
   if (pl.kind == 0) return true;
   if (pl.kind == 2) {
-    if (c->lattice != HLB_D2Q9 || c->p.cd_Q != 1.0) {
-      *why = "the fused tile kernel needs D2Q9 and cd_Q = 1";
+    if (c->lattice != HLB_D2Q9) {
+      *why = "the fused tile kernel needs D2Q9";
       return false;
     }
     if (pl.fuse < 1 || pl.fuse > 5 || pl.fuse == 4) {
@@ -626,7 +631,7 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
 
 ChPlan default_plan(const hlb_ctx *c) {
   ChPlan pl{0, 1, 128, 64};
-  if (c->p.cd_Q != 1.0) return pl;
+  if (c->lattice == HLB_D2Q9 && c->p.cd_Q != 1.0) return pl;
   if (c->lattice == HLB_D3Q19) {
     pl.kind = 1;
     pl.fuse = 1;
@@ -1100,7 +1105,7 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
       }
     }
   }
-  if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
+  if (c->lattice == HLB_D2Q9) {
     for (int fuse : {1, 2, 3, 5})
       for (int to : {16, 32, 48, 64})
         for (int nth : {256, 512, 1024}) {
@@ -1108,6 +1113,8 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
           std::string why;
           if (fuse <= c->m && plan_valid(c, pl, &why)) cand.push_back(pl);
         }
+  }
+  if (c->lattice == HLB_D2Q9 && c->p.cd_Q == 1.0) {
     for (int fuse = 1; fuse <= std::min(c->m, 5); fuse++)
       for (int bw : {64, 128, 256})
         for (int seg : {8, 16, 32, 64, 128, 256}) {

@@ -953,7 +953,8 @@ __device__ __forceinline__ T lane_shift(T v) {
 }
 
 // M convection-diffusion substeps of one TO x TO tile in a single launch
-// (2D, standard 5-point Laplacian).  phi and u* are staged once with a halo
+// (2D; the standard 5-point Laplacian, or with LAP9 the 9-point one of weight
+// cQ on the faces, cR on the diagonals and cC at the centre).  phi and u* are staged once with a halo
 // of 3M; substep s then works on a region that shrinks by 3 on every side
 // (its output region is the next substep's input), entirely in LDS: h with
 // a halo of 2, the diffusion potential with a halo of 1, then phi^{s+1}.
@@ -971,11 +972,13 @@ __device__ __forceinline__ T lane_shift(T v) {
 // west (east) of a vector's first (last) site is the last (first) element
 // of the vector in the previous (next) lane, which holds the previous (next)
 // item of the same row, except at the start (end) of a row and at the
-// edges of the wavefront: there it is read from LDS.  Every phase loop has
+// edges of the wavefront: there it is read from LDS.  The same holds for the
+// rows above and below, whose edge values are the 9-point Laplacian's
+// diagonal neighbours.  Every phase loop has
 // a constant trip count and is unrolled, so that one item's loads can be
 // issued under another's arithmetic.
 // NTH threads per block (256, 512 or 1024).
-template <typename T, int M, int TO, bool FLUX, int NTH>
+template <typename T, int M, int TO, bool FLUX, int NTH, bool LAP9>
 __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
                                                  T *__restrict__ phi_out) {
   using G = FusedTileGeom<T, M, TO>;
@@ -1002,7 +1005,7 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
   }
   __syncthreads();
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
-  const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cC = T(p.cC);
+  const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cR = T(p.cR), cC = T(p.cC);
   const int lane = threadIdx.x & 63;
   auto ld = [](const T *arr, int y, int x) { return *reinterpret_cast<const vec *>(arr + y * P + OFF + x); };
   auto st = [](T *arr, int y, int x, vec v) { *reinterpret_cast<vec *>(arr + y * P + OFF + x) = v; };
@@ -1085,10 +1088,18 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
              const vec hc = ld(sq, y, x), hdn = ld(sq, y - 1, x), hup = ld(sq, y + 1, x);
              const vec ph = ld(sp, y, x);
              const vec hw = west(sq, hc, y, x, i, nq), he = east(sq, hc, y, x, i, nq);
+             vec dg;  // sums of the diagonal neighbours
+             if constexpr (LAP9) {
+               const vec dw = west(sq, hdn, y - 1, x, i, nq), de = east(sq, hdn, y - 1, x, i, nq);
+               const vec uw = west(sq, hup, y + 1, x, i, nq), ue = east(sq, hup, y + 1, x, i, nq);
+#pragma unroll
+               for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
+             }
              vec mu;
 #pragma unroll
              for (int j = 0; j < V; j++) {
-               const T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
+               T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
+               if constexpr (LAP9) Lh += cR * dg[j];
                mu[j] = a * hc[j] + b * ph[j] * ph[j] * ph[j] - kappa * Lh;
              }
              st(sp, y, x, mu);
@@ -1100,10 +1111,18 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
              const vec mc = ld(sp, y, x), mdn = ld(sp, y - 1, x), mup = ld(sp, y + 1, x);
              const vec hc = ld(sq, y, x);
              const vec mw = west(sp, mc, y, x, i, nq), me = east(sp, mc, y, x, i, nq);
+             vec dg;
+             if constexpr (LAP9) {
+               const vec dw = west(sp, mdn, y - 1, x, i, nq), de = east(sp, mdn, y - 1, x, i, nq);
+               const vec uw = west(sp, mup, y + 1, x, i, nq), ue = east(sp, mup, y + 1, x, i, nq);
+#pragma unroll
+               for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
+             }
              vec out;
 #pragma unroll
              for (int j = 0; j < V; j++) {
-               const T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
+               T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
+               if constexpr (LAP9) Lm += cR * dg[j];
                out[j] = hc[j] + dtg * Lm;
              }
              st(sq, y, x, out);

@@ -287,6 +287,36 @@ def test_substep_plans_agree(hlb, plan, storage, nx):
     assert max(d.values()) < tol, (plan, d)
 
 
+@pytest.mark.parametrize("plan", [(2, 3, 64, 1024), (2, 3, 32, 256), (2, 1, 16, 0), (2, 2, 48, 512),
+                                  (2, 3, 16, 1024)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx", [150, 152])
+def test_fused_tiles_isotropic_laplacian(hlb, plan, storage, nx):
+    """The fused tiles with the 9-point convection-diffusion Laplacian
+    (cd_Q = 2/3, the isotropic one, for which the stability bound gives
+    m = 3) against the oracle on ragged 150 x 83 and 152 x 83 lattices:
+    its diagonal neighbours come from the neighbouring lanes' row vectors
+    above and below, or from LDS at row ends and wavefront edges."""
+    es = 8 if storage == "f64" else 4
+    v, h = 16 // es, 3 * plan[1]
+    ha = -(-h // v) * v
+    if 4 * (plan[2] + 2 * h) * (plan[2] + 2 * ha + 2 * v) * es > 163840:
+        pytest.skip("the staged tile exceeds a CU's LDS in this storage")
+    shape = (83, nx)
+    phi = _drop(shape, 20, BASE) + synth.spinodal(shape, seed=6, amp=0.02)
+    u0 = np.zeros((2,) + shape)
+    u0[0], u0[1] = -0.006, 0.009
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=0.3, Q=2.5, cd_Q=2 / 3,
+                     advection=plan[2] // 16 % 2)
+    assert gpu.m == 3
+    gpu.set_plan(*plan)
+    gpu.step(40)
+    ora.step(40)
+    d = _maxdiff(gpu, ora)
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert max(d.values()) < tol, (plan, d)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_fused_plan_on_lattices_smaller_than_the_halo(hlb, storage):
     """The fused kernel's strip and march wrap around lattices narrower or
