@@ -224,10 +224,11 @@ hlb_status validate(int lattice, const hlb_params *p, int *m_out, std::string *m
 
 // Execution plan of the convection-diffusion substeps of a step.
 struct ChPlan {
-  int kind;  // 0: one tiled launch per substep; 1: fused y-march launches (D2Q9, cd_Q = 1)
-  int fuse;  // substeps per fused launch, 1..5
-  int bw;    // columns (threads) per block of the fused kernel: 64, 128 or 256
-  int seg;   // rows per block of the fused kernel
+  int kind;  // 0: one tiled launch per substep; 1: marching launches (y in D2Q9 with cd_Q = 1,
+             // z in D3Q19); 2: fused LDS tiles (D2Q9)
+  int fuse;  // substeps per launch, 1..5 (1 in D3Q19)
+  int bw;    // kind 1: columns per block (D2Q9) or threads per block (D3Q19); kind 2: tile edge
+  int seg;   // kind 1: rows or planes per block; kind 2: threads per block (0 means 256)
 };
 
 struct hlb_ctx {
