@@ -41,7 +41,7 @@ template <> struct Tiles<D3Q19, double> {
   static constexpr int CH[3] = {8, 4, 4};
 };
 template <> struct Tiles<D3Q19, float> {
-  static constexpr int LB[3] = {32, 4, 4};
+  static constexpr int LB[3] = {64, 4, 4};  // 4 sites per thread; measured 3% faster than 32x4x4 at 256^3
   static constexpr int CH[3] = {16, 4, 4};
 };
 
