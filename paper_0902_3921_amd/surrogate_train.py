@@ -71,15 +71,18 @@ def generate(n_traj: int, pairs_per_traj: int = 8, group: int = 250, seed0: int 
 
 
 def train(net, snaps, iters: int, batch: int, lr: float, seed: int = 0, log=print, log_every: int = 200,
-          pushforward: float = 0.0):
+          pushforward: float = 0.0, noise: float = 0.0):
     """Adam on random (state, state + JUMP) pairs, cosine learning-rate decay
     from lr to lr / 100.  With probability `pushforward` (after the first
     third of the iterations) an iteration instead takes the network's own
     prediction of a state one jump ahead as input and the state two jumps
     ahead as target, without a gradient through the first jump (the
     "pushforward" training of Brandstetter, Worrall and Welling), so that the
-    network learns to correct the errors it makes.  Returns the list of
-    (iteration, loss)."""
+    network learns to correct the errors it makes.  With `noise` > 0 every
+    input also receives Gaussian noise of that fraction of each channel's
+    standard deviation over the data, and the target stays clean (noise
+    injection, Sanchez-Gonzalez et al.), for the same purpose.  Returns the
+    list of (iteration, loss)."""
     import torch
 
     n_traj, n_snap = snaps.shape[0], snaps.shape[1]
@@ -88,11 +91,18 @@ def train(net, snaps, iters: int, batch: int, lr: float, seed: int = 0, log=prin
     t0 = time.perf_counter()
     x = torch.empty((batch, SIZE, SIZE, 3), dtype=torch.float32, device="cuda")
     y = torch.empty_like(x)
+    sigma = None
+    if noise > 0:
+        std = torch.stack([snaps[..., c].std() for c in range(3)])
+        sigma = (noise * std).view(1, 1, 1, 3)
+        ngen = torch.Generator(device="cuda").manual_seed(seed + 1)
     for it in range(iters):
         push = it >= iters // 3 and float(torch.rand((), generator=gen)) < pushforward
         ti = torch.randint(0, n_traj, (batch,), generator=gen)
         si = torch.randint(0, n_snap - (2 if push else 1), (batch,), generator=gen)
         x.copy_(snaps[ti.cuda(), si.cuda()])
+        if sigma is not None:
+            x.add_(torch.randn(x.shape, generator=ngen, device="cuda") * sigma)
         if push:
             net.forward(x, x)
             y.copy_(snaps[ti.cuda(), (si + 2).cuda()])
@@ -184,6 +194,7 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--rollout-seed", type=int, default=100000)
     ap.add_argument("--pushforward", type=float, default=0.5)
+    ap.add_argument("--noise", type=float, default=0.0)
     args = ap.parse_args(argv)
 
     import torch
@@ -198,7 +209,8 @@ def main(argv=None):
     print(f"data: {tuple(snaps.shape)} in {time.perf_counter() - t0:.0f} s", flush=True)
     net = sur.Surrogate(batch=args.batch)
     net.set_params(sur.he_init(args.seed))
-    hist = train(net, snaps, args.iters, args.batch, args.lr, args.seed, pushforward=args.pushforward)
+    hist = train(net, snaps, args.iters, args.batch, args.lr, args.seed, pushforward=args.pushforward,
+                 noise=args.noise)
     params = net.params()
     del snaps
     test = sur.Surrogate(batch=1)
@@ -206,7 +218,7 @@ def main(argv=None):
     r = rollout(test, args.rollout_seed)
     free = rollout(test, args.rollout_seed, tol=float("inf"))
     meta = dict(trajectories=args.trajectories, pairs=args.pairs, iters=args.iters, batch=args.batch, lr=args.lr,
-                pushforward=args.pushforward,
+                pushforward=args.pushforward, noise=args.noise,
                 seed=args.seed, final_loss=hist[-1][1], rollout_errors=np.array(r["errors"]),
                 free_rollout_errors=np.array(free["errors"]), loss_history=np.array(hist),
                 recipe="spinodal 256x256 D2Q9 FP32, a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1 N=0.3 Q=2.5, "
