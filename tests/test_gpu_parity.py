@@ -207,16 +207,41 @@ def test_reduce_matches_oracle(hlb):
     np.testing.assert_allclose(rg["mom"], ro["mom"], atol=1e-12)
 
 
-def test_tiny_and_degenerate_lattices(hlb):
-    """Lattices smaller than the stencil reach (periodic images overlap)."""
-    for shape in [(1, 1), (2, 3), (5, 1), (3, 4)]:
-        rng = np.random.default_rng(sum(shape))
-        phi = rng.uniform(-0.5, 0.5, shape)
-        gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=0.3, Q=2.5)
-        gpu.step(7)
-        ora.step(7)
-        d = _maxdiff(gpu, ora)
-        assert max(d.values()) < 1e-13, (shape, d)
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_tiny_and_degenerate_lattices(hlb, storage):
+    """Lattices smaller than the stencil reach (periodic images overlap), with
+    the default plan, the one-substep tiles and the fused tiles (whose staged
+    box wraps many times; widths 4 and 8 take its 16-byte path in FP32)."""
+    tol = 1e-13 if storage == "f64" else 2e-6
+    for shape in [(1, 1), (2, 3), (5, 1), (3, 4), (4, 4), (4, 8)]:
+        for plan in [None, (0, 1, 128, 64), (2, 5, 16, 0), (2, 3, 64, 1024)]:
+            if storage == "f64" and plan == (2, 3, 64, 1024):
+                continue  # exceeds the LDS in FP64
+            rng = np.random.default_rng(sum(shape))
+            phi = rng.uniform(-0.5, 0.5, shape)
+            gpu, ora = _pair(hlb, shape, storage, phi, **BASE, N=0.3, Q=2.5)
+            if plan is not None:
+                gpu.set_plan(*plan)
+            gpu.step(7)
+            ora.step(7)
+            d = _maxdiff(gpu, ora)
+            assert max(d.values()) < tol, (shape, plan, d)
+
+
+@pytest.mark.parametrize("cd_Q", [1.0, 1 / 3], ids=["lap7", "lap19"])
+def test_tiny_d3q19_lattices(hlb, cd_Q):
+    """D3Q19 lattices of one to three sites per axis (every stencil reach is
+    a periodic image), with the tiled and the z-marching substep kernels."""
+    for shape in [(1, 1, 1), (1, 2, 3), (2, 3, 1)]:
+        for plan in [(0, 1, 128, 64), (1, 1, 256, 2), (1, 1, 512, 1)]:
+            rng = np.random.default_rng(sum(shape) + 1)
+            phi = rng.uniform(-0.5, 0.5, shape)
+            gpu, ora = _pair(hlb, shape, "f64", phi, **BASE, N=1 / 6, Q=1 / 3, cd_Q=cd_Q)
+            gpu.set_plan(*plan)
+            gpu.step(5)
+            ora.step(5)
+            d = _maxdiff(gpu, ora)
+            assert max(d.values()) < 1e-13, (shape, plan, d)
 
 
 def test_zero_steps_and_counter(hlb):
