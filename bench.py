@@ -469,6 +469,9 @@ def main():
     kd = r["dominant"]
     alg_launch = kd["bytes_per_lu"] * kd.get("units", r["ns"])
     copy_gbs = copy_rate_gbs(int(alg_launch))
+    # the rocprof fraction: measured HBM bytes per launch over the same launch duration
+    traffic = measured_traffic(args.workload, kd["name"])
+    traffic_gbs = traffic * kd["gbs"] / alg_launch if traffic is not None else None
     out = {
         "metric": "MLUPS & % HBM peak (D2Q9/D3Q19 hybrid step)",
         "value": r["mlups"],
@@ -492,7 +495,9 @@ def main():
                     "stencil": "N=0.3, Q=2.5" if r["d"] == 2 else "N=1/6, Q=1/3",
                     "params": "a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1", "seed": 0}),
         "roofline": {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": measured_traffic(args.workload, kd["name"]),
+                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": traffic_gbs,
+                     "traffic_frac": traffic_gbs / HBM_PEAK_GBS if traffic_gbs is not None else None,
                      "kernel": kd["name"], "bytes_per_lu": kd["bytes_per_lu"],
                      "algorithmic_bytes_per_launch": alg_launch,
                      "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": kd["gbs"] / copy_gbs},
