@@ -271,6 +271,26 @@ def test_nonfinite_state_is_reported(hlb):
     assert gpu.reduce()["finite"]
 
 
+def test_nonfinite_or_nonpositive_initial_fields_are_rejected(hlb):
+    """hlb_init_fields checks its host arrays: a NaN or infinity anywhere, or
+    a density that is not positive, returns HLB_ENONFINITE, and a rejected
+    call leaves the context usable."""
+    shape = (16, 16)
+    gpu = hlb.Sim(shape, "f32", **BASE)
+    bad_phi = np.zeros(shape)
+    bad_phi[3, 5] = np.nan
+    bad_u = np.zeros((2,) + shape)
+    bad_u[1, 2, 2] = np.inf
+    for args in [(bad_phi,), (np.zeros(shape), None, bad_u), (np.zeros(shape), np.zeros(shape)),
+                 (np.zeros(shape), -np.ones(shape))]:
+        with pytest.raises(hlb.HlbError) as ei:
+            gpu.init(*args)
+        assert ei.value.status == hlb.HLB_ENONFINITE
+    gpu.init(np.zeros(shape))
+    gpu.step(2)
+    assert gpu.reduce()["finite"]
+
+
 @pytest.mark.parametrize("plan", [(0, 1, 128, 64), (1, 5, 64, 7), (1, 5, 128, 16), (1, 5, 256, 40),
                                   (1, 2, 64, 9), (1, 3, 128, 100), (1, 1, 64, 1),
                                   (2, 5, 32, 0), (2, 5, 16, 0), (2, 2, 32, 0), (2, 3, 16, 256), (2, 1, 16, 0),
