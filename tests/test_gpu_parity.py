@@ -176,6 +176,21 @@ def test_spinodal_short_horizon(hlb, storage, steps, tol):
     assert d["phi"] < tol and d["u"] < tol, d
 
 
+@pytest.mark.parametrize("storage,steps,tol", [("f64", 100, 1e-11), ("f32", 50, 1e-5)])
+@pytest.mark.parametrize("cd_Q", [1.0, 1 / 3], ids=["lap7", "lap19"])
+def test_d3q19_spinodal_short_horizon(hlb, storage, steps, tol, cd_Q):
+    """D3Q19 spinodal decomposition on 32^3 (the 3D workload's stencils),
+    with the autotuned substep plan, at the same short horizons as in 2D."""
+    shape = (32, 32, 32)
+    phi = synth.spinodal(shape, seed=0)
+    gpu, ora = _pair(hlb, shape, storage, phi, **BASE, N=1 / 6, Q=1 / 3, cd_Q=cd_Q)
+    gpu.autotune()
+    gpu.step(steps)
+    ora.step(steps)
+    d = _maxdiff(gpu, ora)
+    assert d["phi"] < tol and d["u"] < tol, (gpu.plan, d)
+
+
 @pytest.mark.parametrize("shape", [(18, 20, 24), (7, 9, 33)])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_d3q19_drop(hlb, shape, storage):
