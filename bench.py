@@ -6,7 +6,8 @@ D2Q9 spinodal decomposition on a 1024 x 1024 periodic lattice with FP32
 shifted populations (a = -0.1, b = 0.1, kappa = 0.1, tau = 1, Gamma = 1,
 m = 5, the paper's stencil N = 0.3, Q = 2.5), phi ~ U(-0.01, 0.01) from
 seed 0, n = 1, u = 0; the standard stencil (N = 1/2, Q = 1) is timed beside
-it.  Prints one JSON line.
+it, and the 256^3 D3Q19 spinodal (m = 10) is measured as a sub-record.
+Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME]
 """
@@ -101,7 +102,42 @@ def make_inputs(name, shape):
     return synth.spinodal(shape, seed=0)
 
 
-def run_gpu(name, steps, warmup, plan=None):
+def launch_sequence(m: int, plan) -> list:
+    """Substeps of each convection-diffusion launch of one step under a plan
+    (kind, fuse, bw, seg): one per launch for kind 0 and for D3Q19; kind 1
+    fuses up to `fuse`; kind 2 fuses 1, 2, 3 or 5 (4 runs as 3)."""
+    kind, fuse = plan[0], plan[1]
+    out, done = [], 0
+    while done < m:
+        k = 1 if kind == 0 else min(fuse, m - done)
+        if kind == 2 and k == 4:
+            k = 3
+        out.append(k)
+        done += k
+    return out
+
+
+def state_bytes(shape, storage) -> int:
+    """Device bytes of the state a step touches: two population buffers, two
+    phi buffers and u*."""
+    d = len(shape)
+    q = 9 if d == 2 else 19
+    es = 8 if storage == "f64" else 4
+    ns = 1
+    for s in shape:
+        ns *= s
+    return (2 * q + 2 + d) * ns * es
+
+
+MALL_BYTES = 256 << 20  # MI355X Infinity Cache
+
+
+def run_gpu(name, steps, warmup, plan=None, profile_mode=False, variants=True):
+    """Times `steps` steps of a single-lattice workload.  Kernel durations come
+    from hlb_time_kernels (one HIP event pair around many back-to-back
+    launches of one kernel on the library's stream).  In profile mode (a
+    fixed plan) nothing else is launched: no autotuning, no standard-stencil
+    run, no variants, so a profiler's trace holds only the measured plan."""
     import torch
 
     from paper_0902_3921_amd import hlb
@@ -134,64 +170,71 @@ def run_gpu(name, steps, warmup, plan=None):
     sim, secs, stats = timed(kw, plan)
     m = sim.m
     plan = sim.plan
-    # host transfers of the boundary (FP64 host arrays): one hlb_init_fields
-    # (upload + equilibrium kernel) and one hlb_get_fields (readout kernel +
-    # download), for the PCIe-inclusive rate of a run of `steps` steps
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.init(phi0)
-    t_init = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    sim.fields()
-    t_fields = time.perf_counter() - t0
-    # per-kernel durations from HIP events on the library's stream
-    nprof = max(20, min(200, steps))
-    ms_lb, ms_ch = sim.step_timed(nprof)
     names = (sim.kernel_name(0), sim.kernel_name(1))
+    # kernel durations: event pairs around `reps` repetitions each; the
+    # substep launches as they run in a step (after a collide-and-stream
+    # launch), the first launch scaled from its back-to-back share
+    reps = max(20, min(200, steps // 10))
+    us_lb, us_first_b2b, us_ch_b2b, us_ch_step = sim.time_kernels(reps)
+    us_first = us_first_b2b * us_ch_step / us_ch_b2b
+    host_io = None
+    if not profile_mode:
+        # host transfers of the boundary (FP64 host arrays): one hlb_init_fields
+        # (upload + equilibrium kernel) and one hlb_get_fields (readout kernel +
+        # download), for the PCIe-inclusive rate of a run of `steps` steps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.init(phi0)
+        t_init = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sim.fields()
+        t_fields = time.perf_counter() - t0
+        host_io = {"init_ms": t_init * 1e3, "get_fields_ms": t_fields * 1e3,
+                   "pcie_inclusive_mlups": ns * steps / (secs + t_init + t_fields) / 1e6}
     sim.close()
-    sim_sc, secs_sc, _ = timed(dict(kw, **STANDARD_STENCIL), plan)
-    sim_sc.close()
-    # the scheme variants of the method, each with its own autotuned plan
-    variants = {}
-    var_params = {"flux_advection": dict(kw, advection=1), "mu_first_force": dict(kw, force_form=0)}
-    if kw.get("cd_Q", 1.0) == 1.0:
-        var_params["isotropic_ch_laplacian"] = dict(kw, cd_Q=2 / 3 if d == 2 else 1 / 3)
-    for vname, vkw in var_params.items():
-        vsim, vsecs, _ = timed(vkw)
-        variants[vname] = {"mlups": ns * steps / vsecs / 1e6, "m": vsim.m, "substep_plan": list(vsim.plan)}
-        vsim.close()
+    mlups_sc, var_out = None, None
+    if not profile_mode:
+        sim_sc, secs_sc, _ = timed(dict(kw, **STANDARD_STENCIL), plan)
+        sim_sc.close()
+        mlups_sc = ns * steps / secs_sc / 1e6
+    if not profile_mode and variants:
+        # the scheme variants of the method, each with its own autotuned plan
+        var_out = {}
+        var_params = {"flux_advection": dict(kw, advection=1), "mu_first_force": dict(kw, force_form=0)}
+        if kw.get("cd_Q", 1.0) == 1.0:
+            var_params["isotropic_ch_laplacian"] = dict(kw, cd_Q=2 / 3 if d == 2 else 1 / 3)
+        for vname, vkw in var_params.items():
+            vsim, vsecs, _ = timed(vkw)
+            var_out[vname] = {"mlups": ns * steps / vsecs / 1e6, "m": vsim.m, "substep_plan": list(vsim.plan)}
+            vsim.close()
 
     lb_b, ch_b, step_b = algorithmic_bytes(d, q, es)
-    t_lb = ms_lb / nprof * 1e-3            # s per launch
-    ch_launches = m if plan[0] == 0 else -(-m // plan[1])
-    t_ch = ms_ch / (nprof * ch_launches) * 1e-3  # s per launch
-    # a launch reads phi and u* once and writes phi once, however many substeps it fuses
-    ch_b_launch = ch_b
-    per_step = {"lb": t_lb, "ch": t_ch * ch_launches}
+    seq = launch_sequence(m, plan)
+    n_first = sum(1 for k in seq if k == seq[0])
+    # the dominant kernel: the instantiation with the most device time per step
+    per_step = {"lb": us_lb, "ch": us_first * n_first}
     dominant = max(per_step, key=per_step.get)
     if dominant == "lb":
-        achieved = lb_b * ns / t_lb / 1e9
-        kname, kbytes = names[0], lb_b
+        dom = {"name": names[0], "bytes_per_lu": lb_b, "us": us_lb, "launches_per_step": 1}
     else:
-        # a fused plan may end the step with a shorter launch (e.g. 2 + 2 + 1
-        # substeps); the figure is the class average over the step's launches
-        achieved = ch_b * ns / t_ch / 1e9
-        kname = names[1] + (f" (class average over {ch_launches} launches per step)" if ch_launches > 1 else "")
-        kbytes = ch_b
+        # a launch reads phi and u* once and writes phi once, however many substeps it fuses
+        dom = {"name": names[1], "bytes_per_lu": ch_b, "us": us_first, "launches_per_step": n_first,
+               "substeps_per_launch": seq[0]}
+    dom["gbs"] = dom["bytes_per_lu"] * ns / (dom["us"] * 1e-6) / 1e9
     mlups = ns * steps / secs / 1e6
     return {
         "shape": shape, "storage": storage, "desc": desc, "m": m, "ns": ns, "secs": secs,
-        "mlups": mlups, "mlups_standard": ns * steps / secs_sc / 1e6, "variants": variants, "stats": stats,
-        "plan": plan,
-        "host_io": {"init_ms": t_init * 1e3, "get_fields_ms": t_fields * 1e3,
-                    "pcie_inclusive_mlups": ns * steps / (secs + t_init + t_fields) / 1e6},
-        "kernels": {"lb": {"name": names[0], "us_per_launch": t_lb * 1e6, "bytes_per_lu": lb_b,
-                           "gbs": lb_b * ns / t_lb / 1e9},
-                    "ch": {"name": names[1], "us_per_launch": t_ch * 1e6, "launches_per_step": ch_launches,
-                           "substeps_per_launch": m // ch_launches, "bytes_per_lu": ch_b_launch,
-                           "gbs": ch_b_launch * ns / t_ch / 1e9}},
-        "dominant": {"name": kname, "bytes_per_lu": kbytes, "gbs": achieved},
-        "step_min_bytes_per_lu": step_b, "q": q, "d": d, "es": es,
+        "mlups": mlups, "mlups_standard": mlups_sc, "variants": var_out, "stats": stats,
+        "plan": plan, "launches": seq, "host_io": host_io,
+        "kernels": {"lb": {"name": names[0], "us_per_launch": us_lb, "bytes_per_lu": lb_b,
+                           "gbs": lb_b * ns / (us_lb * 1e-6) / 1e9},
+                    "ch": {"name": names[1], "us_per_launch": us_first, "launches": seq,
+                           "us_all_launches_per_step": us_ch_step, "us_all_launches_back_to_back": us_ch_b2b,
+                           "bytes_per_lu": ch_b,
+                           "gbs_all_launches": ch_b * ns * len(seq) / (us_ch_step * 1e-6) / 1e9},
+                    "kernel_us_per_step": us_lb + us_ch_step},
+        "dominant": dom, "step_min_bytes_per_lu": step_b, "q": q, "d": d, "es": es,
+        "mall_resident": state_bytes(shape, storage) < MALL_BYTES,
     }
 
 
@@ -244,9 +287,10 @@ def run_gpu_batch(name, steps, warmup, plan=None):
     chname = {0: f"hlb::k_ch_batch<{tname}, {tile_plan[4]}, {tile_plan[5]}, true>",
               1: f"hlb::k_chf_batch<{tname}, {fuse}, {tile_plan[4]}, true>",
               2: f"hlb::k_chm_batch<{tname}, {fuse}, {tile_plan[4]}>"}[kind]
-    kd = ({"name": lbname, "bytes_per_lu": lb_b, "gbs": lb_gbs, "units": total} if dominant == "lb" else
+    kd = ({"name": lbname, "bytes_per_lu": lb_b, "gbs": lb_gbs, "units": total, "us": t_lb * 1e6}
+          if dominant == "lb" else
           {"name": chname + f" (class average over {nlaunch} launches per step)", "bytes_per_lu": ch_b,
-           "gbs": ch_gbs, "units": launch_sites / nlaunch})
+           "gbs": ch_gbs, "units": launch_sites / nlaunch, "us": t_ch * 1e6})
     return {
         "shape": None, "storage": storage, "desc": desc, "m": f"{min(ms)}..{max(ms)} (mean {sub_sites / total:.2f})",
         "ns": total, "secs": secs, "mlups": total * steps / secs / 1e6, "mlups_standard": None,
@@ -259,7 +303,7 @@ def run_gpu_batch(name, steps, warmup, plan=None):
                            "substeps_per_launch": fuse, "substep_site_updates_per_step": sub_sites,
                            "launch_site_updates_per_step": launch_sites, "bytes_per_lu": ch_b, "gbs": ch_gbs}},
         "dominant": kd, "step_min_bytes_per_lu": step_b, "q": 9, "d": 2, "es": es,
-        "nsim": len(shapes), "sites": total,
+        "nsim": len(shapes), "sites": total, "mall_resident": False,
     }
 
 
@@ -322,33 +366,34 @@ def run_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
-def measured_traffic(name, kernel_name):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 summary of
-    this workload (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the
-    copy calibration), or None if the summary is missing, does not list the
-    kernel, or was taken on different library sources."""
+def profile_figures(name, kernel_name):
+    """From the committed rocprofv3 summary of this workload, for the kernel
+    of exactly this name (the full template instantiation): HBM bytes per
+    dispatch (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the copy
+    calibration) and the kernel-trace average duration in us.  None for a
+    figure the summary does not hold, and for both if the summary was taken
+    on different library sources."""
     from paper_0902_3921_amd import build
 
     path = os.path.join(ROOT, "profiles", f"{name}.md")
     if not os.path.exists(path):
-        return None
+        return None, None
     text = open(path).read()
     if f"library source hash: {build.source_hash()}" not in text:
-        return None
-    # kernels of the same template and storage type (a fused plan mixes launch
-    # lengths); dispatch-weighted average per launch
-    prefix = kernel_name.split("<")[0] + "<" + kernel_name.split("<")[1].split(",")[0] if "<" in kernel_name else kernel_name
-    total, count = 0.0, 0
+        return None, None
+    traffic, avg_us = None, None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) == 4 and cells[0].startswith(prefix):
-            try:
-                n, fetch, write = int(cells[1]), float(cells[2]), float(cells[3])
-            except ValueError:
-                continue
-            total += n * (fetch * 1024 * FETCH_SCALE + write * 1024 * WRITE_SCALE)
-            count += n
-    return total / count if count else None
+        if not cells or cells[0] != kernel_name:
+            continue
+        try:
+            if len(cells) == 4:  # kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB
+                traffic = float(cells[2]) * 1024 * FETCH_SCALE + float(cells[3]) * 1024 * WRITE_SCALE
+            elif len(cells) == 6:  # kernel | calls | avg us | min us | max us | % time
+                avg_us = float(cells[2])
+        except ValueError:
+            continue
+    return traffic, avg_us
 
 
 def copy_rate_gbs(nbytes: int, reps: int = 20) -> float:
@@ -433,6 +478,8 @@ def main():
     ap.add_argument("--plan", default=None,
                     help="plan to use instead of autotuning (e.g. for profiler runs): kind,fuse,bw,seg for one "
                          "simulation, lb,substep candidate indices for a batch")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="leave out the 256^3 D3Q19 sub-record of the default run")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="also run a device copy of this many MiB (for the HBM counter scale)")
     args = ap.parse_args()
@@ -452,8 +499,19 @@ def main():
         run_surrogate(args)
         return
     plan = tuple(int(v) for v in args.plan.split(",")) if args.plan else None
+    profile_mode = plan is not None
     batched = WORKLOADS[args.workload][0] is None
-    r = (run_gpu_batch if batched else run_gpu)(args.workload, args.steps, args.warmup, plan)
+    if batched:
+        r = run_gpu_batch(args.workload, args.steps, args.warmup, plan)
+    else:
+        r = run_gpu(args.workload, args.steps, args.warmup, plan, profile_mode=profile_mode)
+    # the metric's other configuration, the 256^3 D3Q19 spinodal, as a
+    # sub-record of the default run (its own autotuned plan, 200 steps)
+    sub3d = None
+    if args.workload == "d2q9_spinodal_1024" and not profile_mode and not args.no_3d:
+        r3 = run_gpu("d3q19_spinodal_256", min(args.steps, 200), min(args.warmup, 10), variants=False)
+        sub3d = summarize(r3, "d3q19_spinodal_256", min(args.steps, 200))
+        sub3d.pop("host_io", None)
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -465,13 +523,7 @@ def main():
     if not args.no_cpu_baseline and int(os.environ.get("RANK", "0")) == 0:
         cpu = run_cpu_baseline(args.workload)
 
-    ms_per_step = r["secs"] / args.steps * 1e3
-    kd = r["dominant"]
-    alg_launch = kd["bytes_per_lu"] * kd.get("units", r["ns"])
-    copy_gbs = copy_rate_gbs(int(alg_launch))
-    # the rocprof fraction: measured HBM bytes per launch over the same launch duration
-    traffic = measured_traffic(args.workload, kd["name"])
-    traffic_gbs = traffic * kd["gbs"] / alg_launch if traffic is not None else None
+    rec = summarize(r, args.workload, args.steps)
     out = {
         "metric": "MLUPS & % HBM peak (D2Q9/D3Q19 hybrid step)",
         "value": r["mlups"],
@@ -479,7 +531,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": rec["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -489,27 +541,57 @@ def main():
                     "m": r["m"], "tile_plan": list(r["plan"]), "substep_plan": list(r["plan_index"]),
                     "stencil": "N=0.3, Q=2.5",
                     "params": "a=-0.1 b=0.1 Gamma=1, kappa and tau per simulation", "seed": 0}
-                   if batched else
-                   {"workload": r["desc"], "lattice": "D2Q9" if r["d"] == 2 else "D3Q19",
-                    "shape": list(r["shape"]), "m": r["m"], "substep_plan": list(r["plan"]),
-                    "stencil": "N=0.3, Q=2.5" if r["d"] == 2 else "N=1/6, Q=1/3",
-                    "params": "a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1", "seed": 0}),
-        "roofline": {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_gbs": traffic_gbs,
-                     "traffic_frac": traffic_gbs / HBM_PEAK_GBS if traffic_gbs is not None else None,
-                     "kernel": kd["name"], "bytes_per_lu": kd["bytes_per_lu"],
-                     "algorithmic_bytes_per_launch": alg_launch,
-                     "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": kd["gbs"] / copy_gbs},
-        "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
+                   if batched else rec["config"]),
+        "roofline": rec["roofline"],
+        "step_algorithmic_frac": rec["step_algorithmic_frac"],
+        "mall_resident": r["mall_resident"],
         "mlups_standard_stencil": r["mlups_standard"],
         "variants": r.get("variants"),
         "host_io": r.get("host_io"),
         "kernels": r["kernels"],
         "check": {k: r["stats"][k] for k in ("finite", "mass", "umax", "umax_sim") if k in r["stats"]},
+        "d3q19_spinodal_256": sub3d,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def summarize(r, workload, steps):
+    """The roofline record of one run: the dominant kernel's algorithmic
+    bytes per launch over its average launch duration (hlb_time_kernels),
+    against the 8 TB/s HBM peak; the committed profile's measured HBM bytes
+    per launch of that same kernel (exact instantiation) and its kernel-trace
+    average duration, for comparison; and the step's algorithmic fraction."""
+    kd = r["dominant"]
+    alg_launch = kd["bytes_per_lu"] * kd.get("units", r["ns"])
+    traffic, prof_us = profile_figures(workload, kd["name"].split(" (")[0])
+    traffic_gbs = traffic / (kd["us"] * 1e-6) / 1e9 if traffic is not None else None
+    copy_gbs = copy_rate_gbs(int(alg_launch))
+    rec = {
+        "ms_per_step": r["secs"] / steps * 1e3,
+        "mlups": r["mlups"],
+        "config": None if r["shape"] is None else
+        {"workload": r["desc"], "lattice": "D2Q9" if r["d"] == 2 else "D3Q19",
+         "shape": list(r["shape"]), "m": r["m"], "substep_plan": list(r["plan"]),
+         "launches_per_step": r.get("launches"),
+         "stencil": "N=0.3, Q=2.5" if r["d"] == 2 else "N=1/6, Q=1/3",
+         "params": "a=-0.1 b=0.1 kappa=0.1 tau=1 Gamma=1", "seed": 0},
+        "roofline": {"bound": "hbm", "achieved": kd["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": kd["gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_gbs": traffic_gbs,
+                     "traffic_frac": traffic_gbs / HBM_PEAK_GBS if traffic_gbs is not None else None,
+                     "traffic_over_algorithmic": traffic / alg_launch if traffic is not None else None,
+                     "kernel": kd["name"], "bytes_per_lu": kd["bytes_per_lu"],
+                     "algorithmic_bytes_per_launch": alg_launch, "us_per_launch": kd["us"],
+                     "launches_per_step": kd.get("launches_per_step"),
+                     "profile_avg_us": prof_us,
+                     "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": kd["gbs"] / copy_gbs},
+        "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
+        "mall_resident": r["mall_resident"],
+        "kernels": r["kernels"],
+        "check": {k: r["stats"][k] for k in ("finite", "mass", "umax") if k in r["stats"]},
+    }
+    return rec
 
 
 if __name__ == "__main__":

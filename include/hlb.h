@@ -205,16 +205,44 @@ hlb_status hlb_get_plan(const hlb_ctx *ctx, int plan[4]);
  * be NULL).  Synchronises. */
 hlb_status hlb_autotune(hlb_ctx *ctx, double *best_us);
 
-/* Names of the device kernels of a kernel class (0 or 1) for the context's
- * lattice, storage and plan, as they appear in profiler traces. */
+/* Name of a device kernel as profiler traces print it (the full template
+ * instantiation, without "void" and the argument list), for the context's
+ * lattice, storage, parameters and plan: kernel_class 0 is the force +
+ * collide-and-stream kernel, 1 the kernel of the first convection-diffusion
+ * launch of a step (a fused plan may end a step with a launch of fewer
+ * substeps, which is another instantiation).  The string is owned by the
+ * context and valid until its next call; "" for an invalid argument. */
 const char *hlb_kernel_name(const hlb_ctx *ctx, int kernel_class);
+
+/* Average device time of the step's kernels, in microseconds, each measured
+ * with one pair of HIP events around `reps` >= 1 repetitions on the
+ * context's stream (after one untimed repetition of each):
+ *   us[0] = one force + collide-and-stream launch (kernel class 0),
+ *           repeated back to back;
+ *   us[1] = the first convection-diffusion launch of a step (class 1),
+ *           repeated back to back;
+ *   us[2] = all convection-diffusion launches of one step, back to back;
+ *   us[3] = all convection-diffusion launches of one step when each follows
+ *           a collide-and-stream launch, as in a step: the time of `reps`
+ *           such pairs minus that of us[0]'s launches.  Back-to-back
+ *           launches of a kernel whose inputs fit the caches read them
+ *           from there; us[3] includes the refetch after the
+ *           collide-and-stream launch has streamed the populations.
+ * The collide-and-stream launches read the current state and write only the
+ * spare population buffer and u* (which then holds the current state's u*);
+ * the substep launches read phi and u* and write scratch buffers in the
+ * staging area.  The state and the step counter are unchanged.  For
+ * benchmarks and profiles.  Synchronises. */
+hlb_status hlb_time_kernels(hlb_ctx *ctx, int reps, double us[4]);
 
 /* Checkpoints.  A timestep depends only on (f_t, phi_t) and the parameters
  * (Sec. 2: the force, u*, the collision and the substeps are all computed
  * from the state at time t), so a checkpoint holds a header (lattice,
- * storage, size, step counter, hlb_params) and the state in its device
- * representation (populations as stored, then phi), and a resumed run is
- * bit-identical to an uninterrupted one.
+ * storage, size, step counter, hlb_params, and the substep plan, because
+ * plans agree only up to rounding order) and the state in its device
+ * representation (populations as stored, then phi), and a run resumed in any
+ * context of the same lattice, storage and size is bit-identical to an
+ * uninterrupted one.
  *
  * hlb_checkpoint_size: bytes of a checkpoint of this context.
  * hlb_save: writes the checkpoint into the caller's host buffer (at least
@@ -222,8 +250,8 @@ const char *hlb_kernel_name(const hlb_ctx *ctx, int kernel_class);
  *   non-finite state.  Synchronises.
  * hlb_load: restores a checkpoint of a context with the same lattice,
  *   storage and size (HLB_ESHAPE otherwise; HLB_EINVAL for a buffer that is
- *   not a checkpoint or is truncated), including the step counter and the
- *   parameters, and clears the error state.  Synchronises. */
+ *   not a checkpoint or is truncated), including the step counter, the
+ *   parameters and the plan, and clears the error state.  Synchronises. */
 hlb_status hlb_checkpoint_size(const hlb_ctx *ctx, size_t *bytes);
 hlb_status hlb_save(hlb_ctx *ctx, void *host, size_t bytes);
 hlb_status hlb_load(hlb_ctx *ctx, const void *host, size_t bytes);

@@ -434,7 +434,8 @@ struct Ops {
   // The m substeps of one step with the context's plan: the first launch reads
   // `in`, launches alternate between writing b0 and b1.  Returns the number of
   // launches (the result is in b0 if it is odd, else in b1).
-  static int substeps(hlb_ctx *c, const KParams &k, const T *in, T *b0, T *b1) {
+  // With max_launches > 0 only the first max_launches launches are enqueued.
+  static int substeps(hlb_ctx *c, const KParams &k, const T *in, T *b0, T *b1, int max_launches = 0) {
     const T *src = in;
     T *dst = b0;
     int n = 0;
@@ -443,15 +444,16 @@ struct Ops {
       dst = dst == b0 ? b1 : b0;
       n++;
     };
+    const int cap = max_launches > 0 ? max_launches : c->m;
     if (c->plan.kind == 1) {
-      for (int done = 0; done < c->m;) {
+      for (int done = 0; done < c->m && n < cap;) {
         const int M = std::min(c->plan.fuse, c->m - done);
         march(c, k, M, src, dst);
         advance();
         done += M;
       }
     } else if (c->plan.kind == 2) {
-      for (int done = 0; done < c->m;) {
+      for (int done = 0; done < c->m && n < cap;) {
         int M = std::min(c->plan.fuse, c->m - done);
         if (M == 4) M = 3;  // instantiated: 1, 2, 3, 5
         tile(c, k, M, src, dst);
@@ -459,7 +461,7 @@ struct Ops {
         done += M;
       }
     } else {
-      for (int s = 0; s < c->m; s++) {
+      for (int s = 0; s < c->m && n < cap; s++) {
         ch(c, k, src, dst);
         advance();
       }
@@ -869,12 +871,15 @@ hlb_status hlb_get_state(hlb_ctx *c, double *f, double *phi) {
 // an uninterrupted one: a timestep is a function of (f_t, phi_t) and the
 // parameters only, and no kernel depends on anything else.
 namespace {
-constexpr char kCkptMagic[8] = {'H', 'L', 'B', 'C', 'K', 'P', 'T', '1'};
+constexpr char kCkptMagic[8] = {'H', 'L', 'B', 'C', 'K', 'P', 'T', '2'};
 struct CkptHeader {
   char magic[8];
   int lattice, storage, nx, ny, nz, q;
   long long step;
   hlb_params p;
+  int plan[4];  // the substep plan: plans agree only up to rounding order
+  int plan_user;
+  int pad;
 };
 size_t ckpt_bytes(const hlb_ctx *c) {
   const size_t es = c->storage == HLB_F64 ? 8 : 4;
@@ -902,6 +907,11 @@ hlb_status hlb_save(hlb_ctx *c, void *host, size_t bytes) {
   h.q = c->q;
   h.step = c->step;
   h.p = c->p;
+  h.plan[0] = c->plan.kind;
+  h.plan[1] = c->plan.fuse;
+  h.plan[2] = c->plan.bw;
+  h.plan[3] = c->plan.seg;
+  h.plan_user = c->plan_user ? 1 : 0;
   char *dst = static_cast<char *>(host);
   std::memcpy(dst, &h, sizeof h);
   const size_t es = c->storage == HLB_F64 ? 8 : 4;
@@ -941,7 +951,15 @@ hlb_status hlb_load(hlb_ctx *c, const void *host, size_t bytes) {
   c->phicur = 0;
   c->step = h.step;
   c->error_state = false;
-  return hlb_set_params(c, &h.p);
+  s = hlb_set_params(c, &h.p);
+  if (s != HLB_OK) return s;
+  // the saved plan, so that the resumed run rounds exactly as the saved one
+  const ChPlan pl{h.plan[0], h.plan[1], h.plan[2], h.plan[3]};
+  std::string why;
+  if (!plan_valid(c, pl, &why)) return fail(c, HLB_EINVAL, "checkpoint plan: " + why);
+  c->plan = pl;
+  c->plan_user = h.plan_user != 0;
+  return HLB_OK;
 }
 
 hlb_status hlb_step(hlb_ctx *c, long long nsteps) {
@@ -1039,25 +1057,95 @@ hlb_status hlb_reduce(hlb_ctx *c, hlb_stats *out) {
 
 const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
   if (!c || cls < 0 || cls > 1) return "";
-  if (cls == 1 && c->plan.kind == 2) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "hlb::k_ch_tile<%s, %d, %d>", c->storage == HLB_F64 ? "double" : "float",
-             std::min(c->plan.fuse, c->m), c->plan.bw);
-    const_cast<hlb_ctx *>(c)->names[1] = buf;
-  } else if (cls == 1 && c->plan.kind == 1) {
-    hlb_ctx *mc = const_cast<hlb_ctx *>(c);
-    char buf[160];
-    if (c->lattice == HLB_D3Q19)
-      snprintf(buf, sizeof buf, "hlb::%s<%s, %d threads>", c->p.cd_Q == 1.0 ? "k_ch_march3" : "k_ch_march3w",
-               c->storage == HLB_F64 ? "double" : "float", c->plan.bw);
-    else
-      snprintf(buf, sizeof buf, "hlb::k_ch_march<%s, %d, %d>", c->storage == HLB_F64 ? "double" : "float",
-               std::min(c->plan.fuse, c->m), c->plan.bw);
-    mc->names[1] = buf;
-  } else if (cls == 1) {
-    const_cast<hlb_ctx *>(c)->names[1] = kernel_names(c->lattice, c->storage, 1);
+  hlb_ctx *mc = const_cast<hlb_ctx *>(c);
+  const char *ty = c->storage == HLB_F64 ? "double" : "float";
+  const char *lat = c->lattice == HLB_D2Q9 ? "hlb::D2Q9" : "hlb::D3Q19";
+  const char *flux = c->p.advection == 1 ? "true" : "false";
+  char buf[192];
+  if (cls == 0) {
+    int t[3];
+    dispatch(mc, [&](auto ops) {
+      using O = decltype(ops);
+      t[0] = O::LB0;
+      t[1] = O::LB1;
+      t[2] = O::LB2;
+    });
+    snprintf(buf, sizeof buf, "hlb::k_lb<%s, %s, %d, %d, %d>", lat, ty, t[0], t[1], t[2]);
+  } else if (c->plan.kind == 2) {
+    int M = std::min(c->plan.fuse, c->m);
+    if (M == 4) M = 3;
+    const int nth = c->plan.seg == 1024 ? 1024 : (c->plan.seg == 512 ? 512 : 256);
+    snprintf(buf, sizeof buf, "hlb::k_ch_tile<%s, %d, %d, %s, %d, %s>", ty, M, c->plan.bw, flux, nth,
+             c->p.cd_Q != 1.0 ? "true" : "false");
+  } else if (c->plan.kind == 1 && c->lattice == HLB_D3Q19) {
+    const int txi = c->plan.bw == 256 ? 16 : (c->plan.bw == 512 ? 32 : 64);
+    snprintf(buf, sizeof buf, "hlb::%s<%s, %d, %d, %s>", c->p.cd_Q == 1.0 ? "k_ch_march3" : "k_ch_march3w", ty,
+             txi, 16, flux);
+  } else if (c->plan.kind == 1) {
+    snprintf(buf, sizeof buf, "hlb::k_ch_march<%s, %d, %d, %s>", ty, std::min(c->plan.fuse, c->m), c->plan.bw,
+             flux);
+  } else {
+    int t[3];
+    dispatch(mc, [&](auto ops) {
+      using O = decltype(ops);
+      t[0] = O::CH0;
+      t[1] = O::CH1;
+      t[2] = O::CH2;
+    });
+    snprintf(buf, sizeof buf, "hlb::k_ch<%s, %s, %d, %d, %d, %s>", lat, ty, t[0], t[1], t[2],
+             c->p.cd_Q == 1.0 ? "true" : "false");
   }
+  mc->names[cls] = buf;
   return c->names[cls].c_str();
+}
+
+hlb_status hlb_time_kernels(hlb_ctx *c, int reps, double us[4]) {
+  hlb_status s = usable(c);
+  if (s != HLB_OK) return s;
+  if (reps < 1 || !us) return fail(c, HLB_EINVAL, "reps must be >= 1 and us non-NULL");
+  hipEvent_t ev[5];
+  for (auto &e : ev) {
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return hip_fail(c, r, "hipEventCreate");
+  }
+  const KParams k = kparams(c);
+  // The collide-and-stream launch reads the current populations and phi and
+  // writes the spare population buffer and u*: repeating it leaves the state
+  // as it was, and u* then holds the current state's u*, which the substep
+  // launches read.  The substep launches read the current phi and write two
+  // scratch buffers in the staging area.
+  auto enqueue = [&](int what) {
+    dispatch(c, [&](auto ops) {
+      using T = typename decltype(ops)::Type;
+      T *scratch = at<T>(c, c->lay.io);
+      const T *phi = at<T>(c, c->lay.phi[c->phicur]);
+      if (what == 0 || what == 3) ops.lb(c, k);
+      if (what == 1) ops.substeps(c, k, phi, scratch, scratch + c->ns, 1);
+      if (what == 2 || what == 3) ops.substeps(c, k, phi, scratch, scratch + c->ns);
+    });
+  };
+  for (int w = 0; w < 4; w++) enqueue(w);  // warm-up
+  (void)hipEventRecord(ev[0], c->stream);
+  for (int w = 0; w < 4; w++) {
+    for (int r = 0; r < reps; r++) enqueue(w);
+    (void)hipEventRecord(ev[w + 1], c->stream);
+  }
+  s = launch_check(c, "timed launches");
+  if (s == HLB_OK) s = sync(c);
+  if (s == HLB_OK) {
+    double t[4];
+    for (int w = 0; w < 4; w++) {
+      float ms = 0;
+      (void)hipEventElapsedTime(&ms, ev[w], ev[w + 1]);
+      t[w] = ms * 1e3 / reps;
+    }
+    us[0] = t[0];
+    us[1] = t[1];
+    us[2] = t[2];
+    us[3] = t[3] - t[0];  // whole steps minus the collide-and-stream launches
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  return s;
 }
 
 hlb_status hlb_set_plan(hlb_ctx *c, const int plan[4]) {

@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ESHAPE", -3: "HLB_EUNSTA
 # every symbol include/hlb.h declares
 EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_create",
            "hlb_set_params", "hlb_get_params", "hlb_init_fields", "hlb_set_state", "hlb_get_state",
-           "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name",
+           "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name", "hlb_time_kernels",
            "hlb_set_plan", "hlb_get_plan", "hlb_autotune", "hlb_last_error", "hlb_destroy", "hlb_version",
            "hlb_checkpoint_size", "hlb_save", "hlb_load",
            "hlb_batch_workspace_size", "hlb_batch_create", "hlb_batch_info", "hlb_batch_init_fields",
@@ -91,6 +91,7 @@ def load():
         "hlb_reduce": (st, [_vp, ctypes.POINTER(Stats)]),
         "hlb_step_timed": (st, [_vp, ctypes.c_longlong, _dp]),
         "hlb_kernel_name": (ctypes.c_char_p, [_vp, ctypes.c_int]),
+        "hlb_time_kernels": (st, [_vp, ctypes.c_int, _dp]),
         "hlb_set_plan": (st, [_vp, ctypes.POINTER(ctypes.c_int)]),
         "hlb_get_plan": (st, [_vp, ctypes.POINTER(ctypes.c_int)]),
         "hlb_autotune": (st, [_vp, _dp]),
@@ -310,6 +311,14 @@ class Sim:
 
     def kernel_name(self, cls: int) -> str:
         return self.lib.hlb_kernel_name(self.ctx, cls).decode()
+
+    def time_kernels(self, reps: int):
+        """(us per collide-and-stream launch, us per first substep launch,
+        us of all substep launches of a step, the same after a
+        collide-and-stream launch as in a step); see hlb_time_kernels."""
+        us = (ctypes.c_double * 4)()
+        _check(self.lib.hlb_time_kernels(self.ctx, int(reps), us), self.ctx)
+        return tuple(float(v) for v in us)
 
     # -- readout
     def fields(self):

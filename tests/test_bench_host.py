@@ -32,17 +32,49 @@ def test_algorithmic_bytes_per_lattice_update(d, q, es, lb, ch, step):
     assert bench.algorithmic_bytes(d, q, es) == (lb, ch, step)
 
 
-def test_measured_traffic_from_committed_profiles():
-    """Each committed summary lists its dominant kernel with FETCH_SIZE and
-    WRITE_SIZE; the lookup scales them by the copy calibration, and returns
-    None for a kernel it does not list or a workload without a summary."""
-    t = bench.measured_traffic("d2q9_spinodal_4096", "hlb::k_lb<hlb::D2Q9, float, ...>")
-    if t is None:
-        pytest.skip("the committed summary was taken on other library sources")
-    alg = 84 * 4096 * 4096
-    assert 0.95 * alg < t < 1.2 * alg  # within a few percent of the algorithmic bytes at 4096^2
-    assert bench.measured_traffic("d2q9_spinodal_4096", "hlb::no_such_kernel<float>") is None
-    assert bench.measured_traffic("no_such_workload", "hlb::k_lb<hlb::D2Q9, float, ...>") is None
+def test_profile_figures_match_the_exact_instantiation(tmp_path, monkeypatch):
+    """The traffic and the kernel-trace duration come from the summary rows
+    of exactly the dominant kernel's instantiation, not from other
+    instantiations of the same template (autotuning candidates), and only
+    from a summary taken on the current library sources."""
+    from paper_0902_3921_amd import build
+
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rows = [
+        f"library source hash: {build.source_hash()}",
+        "| kernel | calls | avg us | min us | max us | % time |",
+        "|---|---|---|---|---|---|",
+        "| hlb::k_ch_tile<float, 5, 64, false, 1024, false> | 40 | 19.50 | 18.0 | 21.0 | 40.0 |",
+        "| hlb::k_ch_tile<float, 5, 64, false, 512, false> | 4 | 22.00 | 21.0 | 23.0 | 1.0 |",
+        "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |",
+        "|---|---|---|---|",
+        "| hlb::k_ch_tile<float, 5, 64, false, 1024, false> | 10 | 7000.0 | 4096.0 |",
+        "| hlb::k_ch_tile<float, 5, 64, false, 512, false> | 4 | 9000.0 | 4096.0 |",
+    ]
+    (prof / "w.md").write_text("\n".join(rows) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    t, us = bench.profile_figures("w", "hlb::k_ch_tile<float, 5, 64, false, 1024, false>")
+    assert us == 19.5
+    assert t == 7000.0 * 1024 * bench.FETCH_SCALE + 4096.0 * 1024 * bench.WRITE_SCALE
+    assert bench.profile_figures("w", "hlb::k_ch_tile<float, 5, 64>") == (None, None)
+    assert bench.profile_figures("missing", "x") == (None, None)
+    (prof / "w.md").write_text("\n".join(["library source hash: 0000"] + rows[1:]) + "\n")
+    assert bench.profile_figures("w", "hlb::k_ch_tile<float, 5, 64, false, 1024, false>") == (None, None)
+
+
+@pytest.mark.parametrize("m,plan,seq", [
+    (5, (2, 5, 64, 1024), [5]), (5, (1, 2, 128, 64), [2, 2, 1]), (5, (0, 1, 128, 64), [1] * 5),
+    (10, (1, 1, 1024, 52), [1] * 10), (4, (2, 5, 32, 256), [3, 1]), (8, (2, 5, 32, 256), [5, 3]),
+])
+def test_launch_sequence(m, plan, seq):
+    assert bench.launch_sequence(m, plan) == seq
+
+
+def test_mall_residency():
+    assert bench.state_bytes((1024, 1024), "f32") < bench.MALL_BYTES
+    assert bench.state_bytes((4096, 4096), "f32") > bench.MALL_BYTES
+    assert bench.state_bytes((256, 256, 256), "f32") > bench.MALL_BYTES
 
 
 @pytest.mark.parametrize("name", [n for n, w in bench.WORKLOADS.items() if w[0] is not None])

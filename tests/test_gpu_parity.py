@@ -110,15 +110,18 @@ def test_drop_128_fp64_1000_steps(hlb):
     assert d["phi"] < 1e-11 and d["u"] < 1e-12 and d["n"] < 1e-12, d
 
 
-def test_drop_128_fp32_1000_steps(hlb):
-    """Same workload with FP32 shifted populations: max |dphi|, |du| <= 1e-5."""
+@pytest.mark.parametrize("stencil", [OC, SC, ISO], ids=["paper", "standard", "isotropic"])
+def test_drop_128_fp32_1000_steps(hlb, stencil):
+    """Same workload with FP32 shifted populations: max |dphi|, |du| <= 1e-5,
+    with the paper's optimal stencil, the standard one and the isotropic
+    one (N = 1/3, Q = 2/3)."""
     shape = (128, 128)
     phi = _drop(shape, 20, BASE)
-    gpu, ora = _pair(hlb, shape, "f32", phi, **BASE, N=0.3, Q=2.5)
+    gpu, ora = _pair(hlb, shape, "f32", phi, **BASE, N=stencil[0], Q=stencil[1])
     gpu.step(1000)
     ora.step(1000)
     d = _maxdiff(gpu, ora)
-    print("fp32 drop 1000 steps max diffs", d, flush=True)
+    print(f"fp32 drop 1000 steps, N = {stencil[0]:.4f}, Q = {stencil[1]:.4f}: max diffs", d, flush=True)
     assert d["phi"] <= 1e-5 and d["u"] <= 1e-5, d
 
 
@@ -511,3 +514,66 @@ def test_checkpoint_resume_bit_exact(hlb, storage):
     assert e.value.status == hlb.HLB_EINVAL
     buf = ctypes.create_string_buffer(16)
     assert lib.hlb_save(b.ctx, buf, 16) == hlb.HLB_EINVAL
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_checkpoint_keeps_the_plan(hlb, storage):
+    """Plans agree only up to rounding order, so a checkpoint carries the
+    substep plan: a run saved under a non-default plan (here a 2 + 2 + 1
+    march, and the autotuned plan) and resumed in a fresh context, which
+    starts with the default plan, is bit for bit the uninterrupted run."""
+    shape = (64, 96)
+    phi = _drop(shape, 14, BASE)
+    for plan in ((1, 2, 64, 16), None):
+        a = hlb.Sim(shape, storage, **BASE, N=0.3, Q=2.5)
+        a.init(phi)
+        if plan is None:
+            a.autotune()
+        else:
+            a.set_plan(*plan)
+        a.step(5)
+        blob = a.save()
+        saved_plan = a.plan
+        a.step(11)
+        fa = a.fields()
+        b = hlb.Sim(shape, storage, **BASE, N=0.3, Q=2.5)
+        b.load(blob)
+        assert b.plan == saved_plan
+        b.step(11)
+        fb = b.fields()
+        for k in fa:
+            assert np.array_equal(fa[k], fb[k]), (plan, k)
+        a.close()
+        b.close()
+
+
+def test_kernel_names_and_timing_leave_the_state_alone(hlb):
+    """hlb_kernel_name gives the profiler's names of the instantiations a
+    step launches, and hlb_time_kernels neither changes the state nor the
+    step counter: a run with timings in between equals one without."""
+    shape = (96, 128)
+    phi = _drop(shape, 20, BASE)
+    a = hlb.Sim(shape, "f32", **BASE, N=0.3, Q=2.5)
+    b = hlb.Sim(shape, "f32", **BASE, N=0.3, Q=2.5)
+    for s in (a, b):
+        s.init(phi)
+        s.set_plan(2, 5, 32, 256)
+    assert a.kernel_name(0) == "hlb::k_lb<hlb::D2Q9, float, 64, 8, 1>"
+    assert a.kernel_name(1) == "hlb::k_ch_tile<float, 5, 32, false, 256, false>"
+    a.step(3)
+    us = a.time_kernels(5)
+    assert all(u > 0 for u in us) and us[2] >= 0.9 * us[1]  # one launch per step here
+    a.step(4)
+    b.step(7)
+    assert a.reduce()["step"] == 7
+    fa, fb = a.fields(), b.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    a.set_plan(1, 2, 64, 16)
+    assert a.kernel_name(1) == "hlb::k_ch_march<float, 2, 64, false>"
+    a.set_plan(0, 1, 128, 64)
+    assert a.kernel_name(1) == "hlb::k_ch<hlb::D2Q9, float, 64, 16, 1, true>"
+    c = hlb.Sim((16, 16, 16), "f32", **BASE, N=1 / 6, Q=1 / 3, advection=1)
+    c.set_plan(1, 1, 512, 8)
+    assert c.kernel_name(0) == "hlb::k_lb<hlb::D3Q19, float, 64, 4, 4>"
+    assert c.kernel_name(1) == "hlb::k_ch_march3<float, 32, 16, true>"

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import synth
+from paper_0902_3921_amd import hlb as hlb_mod
 
 pytestmark = pytest.mark.gpu
 
@@ -131,3 +132,51 @@ def test_laplace_law_3d(hlb, cd_Q, m):
           f"{np.round(dp / (2 * sigma * inv_r), 4)}", flush=True)
     assert abs(slope / (2 * sigma) - 1) < 0.08
     assert np.all(np.abs(dp / (2 * sigma * inv_r) - 1) < 0.12)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_flux_advection_conserves_total_phi(hlb, storage):
+    """The flux-form advection (the conservative option beside Eq. adv)
+    together with Eq. diff, whose Laplacian weights sum to zero, conserves
+    sum phi: over 1500 steps of the 128^2 drop it stays at its initial value
+    to 1e-12 relative in FP64.  In FP32 each site's update rounds once per
+    substep, so the sum wanders by float rounding only (bound 1e-6
+    relative); the paper's form drifts by 1e-4 in the same run."""
+    a, kappa = BASE["a"], BASE["kappa"]
+    L = 128
+    phi0 = synth.drop((L, L), 20, 1.0, _w(a, kappa))
+    drift = {}
+    for adv in (1, 0):
+        sim = hlb.Sim((L, L), storage, **BASE, N=0.3, Q=2.5, advection=adv)
+        sim.init(phi0)
+        r0 = sim.reduce()
+        sim.step(1500)
+        r1 = sim.reduce()
+        drift[adv] = abs(r1["phi_sum"] / r0["phi_sum"] - 1)
+        assert r1["finite"] and abs(r1["mass"] / r0["mass"] - 1) < 1e-9
+        sim.close()
+    print(f"{storage}: relative sum-phi drift over 1500 steps: flux form {drift[1]:.3e}, "
+          f"paper form {drift[0]:.3e}", flush=True)
+    assert drift[1] < (1e-12 if storage == "f64" else 1e-6)
+    assert drift[0] > 100 * drift[1]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_reduce_reports_a_state_outside_the_low_mach_regime(hlb, storage):
+    """Sec. 2.1 derives the scheme for small Mach number; hlb_reduce reports
+    HLB_EUNSTABLE when max |u*| >= c_s / 2.  A uniform flow at |u| = 0.3
+    (above c_s / 2 = 0.2887) is reported after it has been stepped; the
+    kernels run normally, the state stays usable, and a flow at |u| = 0.25
+    is accepted."""
+    shape = (32, 48)
+    for speed, expect in ((0.3, hlb_mod.HLB_EUNSTABLE), (0.25, hlb_mod.HLB_OK)):
+        sim = hlb.Sim(shape, storage, **BASE, N=0.3, Q=2.5)
+        u = synth.uniform_velocity(shape, (speed * 0.6, speed * 0.8))
+        sim.init(np.zeros(shape), None, u)
+        sim.step(3)
+        r = sim.reduce(raise_on_error=False)
+        assert r["status"] == expect, (speed, r)
+        assert r["finite"] and abs(r["umax"] - speed) < 1e-6
+        sim.step(2)  # a state reported as outside the regime can still be stepped
+        assert sim.reduce(raise_on_error=False)["step"] == 5
+        sim.close()
