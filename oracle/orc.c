@@ -41,7 +41,14 @@
  *     option;
  *   - an upwind tie (u = 0) takes the forward difference (the product with u
  *     is zero either way);
- *   - an opt-in flux-form advection conserves sum(phi) exactly.
+ *   - an opt-in flux-form advection conserves sum(phi) exactly;
+ *   - the D2Q5 alternative that Sec. 2 mentions (the convection-diffusion
+ *     equation on its own five-velocity lattice, the full-LB variant of the
+ *     memory comparison) is an option of the D2Q9 case: populations h_i on
+ *     c_0 = 0 and the four axis vectors, weights 1/3 and 1/6, with
+ *     phi = sum h_i, sum h^eq c = phi u* and sum h^eq c c = Gamma_h mu I,
+ *     relaxed with tau_phi and streamed like f; its mobility is
+ *     Gamma = Gamma_h (tau_phi - 1/2), so Gamma_h = Gamma / (tau_phi - 1/2).
  */
 #include <math.h>
 #include <stdlib.h>
@@ -290,6 +297,31 @@ int orc_source(int d, double tau, const double *u, const double *F, double *S) {
 }
 
 /* ------------------------------------------------------------------------ */
+/* D2Q5 lattice Boltzmann for the convection-diffusion equation (the        */
+/* alternative named in Sec. 2; the paper solves Eq. convdiffeqn by finite  */
+/* differences instead).  Velocities c_0 = 0, c_1..c_4 along +x, +y, -x, -y; */
+/* weights 1/3 and 1/6, so that sum w c c = c_s^2 I with c_s^2 = 1/3.       */
+/* ------------------------------------------------------------------------ */
+static const int E5[5][2] = {{0, 0}, {1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+static const double W5[5] = {1.0 / 3.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0, 1.0 / 6.0};
+
+/* Equilibrium whose moments are sum h^eq = phi, sum h^eq c = phi u and
+ * sum h^eq c c = Gamma_h mu I (what Eq. convdiffeqn needs at first order):
+ *   h_i^eq = w_i (Gamma_h mu + phi c_i.u) / c_s^2   (i = 1..4),
+ *   h_0^eq = phi - sum_{i>0} h_i^eq. */
+int orc_feq5(double phi, double mu, const double *u, double gamma_h, double *heq) {
+  int i;
+  double rest = phi;
+  for (i = 1; i < 5; i++) {
+    double cu = E5[i][0] * u[0] + E5[i][1] * u[1];
+    heq[i] = W5[i] * (gamma_h * mu + phi * cu) / CS2;
+    rest -= heq[i];
+  }
+  heq[0] = rest;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Convection-diffusion substeps (Sec. 2.3).                                */
 /* ------------------------------------------------------------------------ */
 
@@ -392,6 +424,8 @@ typedef struct {
   int force_form;                 /* 1: expanded (a phi + 3 b phi^3) grad phi - kappa phi grad lap phi; 0: phi grad mu */
   int advection;                  /* 0: the paper's Eq. adv; 1: conservative flux form */
   double g[3];                    /* uniform body acceleration: G = n g added to F */
+  int cd_model;                   /* 0: finite differences (Sec. 2.3); 1: D2Q5 lattice Boltzmann */
+  double tau_phi;                 /* relaxation time of the D2Q5 populations (cd_model 1) */
 } orc_params;
 
 typedef struct {
@@ -399,9 +433,12 @@ typedef struct {
   orc_params p;
   int q;
   double *f;   /* f[i*ns + idx], populations at time t after streaming */
-  double *phi; /* order parameter at time t */
+  double *phi; /* order parameter at time t (cd_model 1: sum of h) */
+  double *h;   /* cd_model 1: h[i*ns + idx], D2Q5 populations at time t after streaming */
   long long step;
 } orc_ctx;
+
+void orc_destroy(orc_ctx *c);
 
 orc_ctx *orc_create(int d, int nx, int ny, int nz, const orc_params *p) {
   orc_ctx *c;
@@ -413,6 +450,11 @@ orc_ctx *orc_create(int d, int nx, int ny, int nz, const orc_params *p) {
   c->q = nvel(d);
   c->f = (double *)calloc((size_t)c->q * c->g.ns, sizeof(double));
   c->phi = (double *)calloc((size_t)c->g.ns, sizeof(double));
+  c->h = (double *)calloc((size_t)5 * c->g.ns, sizeof(double));
+  if (p->cd_model == 1 && (d != 2 || !(p->tau_phi > 0.5))) {
+    orc_destroy(c);
+    return NULL;
+  }
   return c;
 }
 
@@ -420,16 +462,21 @@ void orc_destroy(orc_ctx *c) {
   if (!c) return;
   free(c->f);
   free(c->phi);
+  free(c->h);
   free(c);
 }
 
 int orc_set_params(orc_ctx *c, const orc_params *p) {
   if (!c || !p || p->m < 1) return -1;
+  if (p->cd_model == 1 && (c->g.d != 2 || !(p->tau_phi > 0.5))) return -1;
   c->p = *p;
   return 0;
 }
 
-/* f_i = f_i^eq(n0, u0) at every site (initial populations). */
+static void d2q5_init(orc_ctx *c, const double *u);
+
+/* f_i = f_i^eq(n0, u0) at every site (initial populations); with the D2Q5
+ * convection-diffusion model also h_i = h_i^eq(phi0, mu0, u0). */
 int orc_init(orc_ctx *c, const double *phi, const double *n, const double *u) {
   long idx;
   int i, k;
@@ -440,6 +487,7 @@ int orc_init(orc_ctx *c, const double *phi, const double *n, const double *u) {
     for (i = 0; i < c->q; i++) c->f[i * c->g.ns + idx] = feq[i];
     c->phi[idx] = phi[idx];
   }
+  if (c->p.cd_model == 1) d2q5_init(c, u);
   c->step = 0;
   return 0;
 }
@@ -535,6 +583,87 @@ static void velocity(const grid *g, const double *n, const double *j, const doub
   }
 }
 
+/* Chemical potential of the D2Q5 model: mu = a phi + b phi^3 - kappa L phi
+ * with the Laplacian of the convection-diffusion step (cd_Q), as in
+ * Eq. diff, so that the two models share their equilibria. */
+static void d2q5_mu(const orc_ctx *c, double *mu) {
+  const grid *g = &c->g;
+  const orc_params *p = &c->p;
+  long i;
+  double *lap = (double *)malloc(sizeof(double) * g->ns);
+  apply_lap(g, p->cd_Q, c->phi, lap);
+  for (i = 0; i < g->ns; i++)
+    mu[i] = p->a * c->phi[i] + p->b * c->phi[i] * c->phi[i] * c->phi[i] - p->kappa * lap[i];
+  free(lap);
+}
+
+/* phi = sum_i h_i, summed in the order i = 0..4. */
+static void d2q5_phi(orc_ctx *c) {
+  long idx;
+  int i;
+  for (idx = 0; idx < c->g.ns; idx++) {
+    double s = 0.0;
+    for (i = 0; i < 5; i++) s += c->h[i * c->g.ns + idx];
+    c->phi[idx] = s;
+  }
+}
+
+static void d2q5_init(orc_ctx *c, const double *u) {
+  const grid *g = &c->g;
+  long idx;
+  int i;
+  double gamma_h = c->p.gamma / (c->p.tau_phi - 0.5);
+  double *mu = (double *)malloc(sizeof(double) * g->ns);
+  d2q5_mu(c, mu);
+  for (idx = 0; idx < g->ns; idx++) {
+    double uu[2] = {u[idx], u[g->ns + idx]}, heq[5];
+    orc_feq5(c->phi[idx], mu[idx], uu, gamma_h, heq);
+    for (i = 0; i < 5; i++) c->h[i * g->ns + idx] = heq[i];
+  }
+  free(mu);
+  d2q5_phi(c);
+}
+
+/* One D2Q5 step with u* of this step: BGK relaxation with tau_phi towards
+ * h^eq(phi, mu, u*), then streaming h_i(r + c_i, t + 1) = h_i^post(r). */
+static void d2q5_step(orc_ctx *c, const double *u) {
+  const grid *g = &c->g;
+  const orc_params *p = &c->p;
+  long ns = g->ns, idx;
+  double gamma_h = p->gamma / (p->tau_phi - 0.5);
+  double *mu = (double *)malloc(sizeof(double) * ns);
+  double *hnew = (double *)malloc(sizeof(double) * ns * 5);
+  d2q5_mu(c, mu);
+  for (idx = 0; idx < ns; idx++) {
+    int x = (int)(idx % g->nx), y = (int)(idx / g->nx), i;
+    double uu[2] = {u[idx], u[ns + idx]}, heq[5];
+    orc_feq5(c->phi[idx], mu[idx], uu, gamma_h, heq);
+    for (i = 0; i < 5; i++) {
+      double hi = c->h[i * ns + idx];
+      double post = hi - (hi - heq[i]) / p->tau_phi;
+      hnew[i * ns + site(g, x, y, 0, E5[i][0], E5[i][1], 0)] = post;
+    }
+  }
+  memcpy(c->h, hnew, sizeof(double) * ns * 5);
+  d2q5_phi(c);
+  free(mu);
+  free(hnew);
+}
+
+int orc_get_h(const orc_ctx *c, double *h) {
+  if (!c || c->p.cd_model != 1) return -1;
+  memcpy(h, c->h, sizeof(double) * 5 * c->g.ns);
+  return 0;
+}
+
+/* Sets the D2Q5 populations and phi = sum h. */
+int orc_set_h(orc_ctx *c, const double *h) {
+  if (!c || c->p.cd_model != 1) return -1;
+  memcpy(c->h, h, sizeof(double) * 5 * c->g.ns);
+  d2q5_phi(c);
+  return 0;
+}
+
 /* One timestep t -> t+1. */
 static void one_step(orc_ctx *c) {
   const grid *g = &c->g;
@@ -577,16 +706,21 @@ static void one_step(orc_ctx *c) {
     }
   }
 
-  /* m convection-diffusion substeps with u*_t held fixed (Sec. 2.3). */
-  memcpy(phis, c->phi, sizeof(double) * ns);
-  for (s = 0; s < p->m; s++) {
-    ch_advect(g, dt, p->advection, phis, u, h);
-    ch_diffuse(g, dt, p->gamma, p->a, p->b, p->kappa, p->cd_Q, h, phis, phin);
-    memcpy(phis, phin, sizeof(double) * ns);
+  if (p->cd_model == 1) {
+    /* the D2Q5 alternative: one lattice Boltzmann step of phi with u*_t */
+    d2q5_step(c, u);
+  } else {
+    /* m convection-diffusion substeps with u*_t held fixed (Sec. 2.3). */
+    memcpy(phis, c->phi, sizeof(double) * ns);
+    for (s = 0; s < p->m; s++) {
+      ch_advect(g, dt, p->advection, phis, u, h);
+      ch_diffuse(g, dt, p->gamma, p->a, p->b, p->kappa, p->cd_Q, h, phis, phin);
+      memcpy(phis, phin, sizeof(double) * ns);
+    }
+    memcpy(c->phi, phis, sizeof(double) * ns);
   }
 
   memcpy(c->f, fnew, sizeof(double) * ns * c->q);
-  memcpy(c->phi, phis, sizeof(double) * ns);
   c->step++;
   (void)i;
   (void)k;

@@ -44,6 +44,7 @@ class OrcParams(ctypes.Structure):
         ("N", ctypes.c_double), ("Q", ctypes.c_double), ("cd_Q", ctypes.c_double),
         ("m", ctypes.c_int), ("force_form", ctypes.c_int), ("advection", ctypes.c_int),
         ("g", ctypes.c_double * 3),
+        ("cd_model", ctypes.c_int), ("tau_phi", ctypes.c_double),
     ]
 
 
@@ -79,6 +80,9 @@ def _load():
     lib.orc_source.argtypes = [ctypes.c_int, ctypes.c_double, _dp, _dp, _dp]
     lib.orc_ch_advect.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double, ctypes.c_int, _dp, _dp, _dp]
     lib.orc_ch_diffuse.argtypes = [ctypes.c_int] * 4 + [ctypes.c_double] * 6 + [_dp, _dp, _dp]
+    lib.orc_feq5.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp]
+    lib.orc_get_h.argtypes = [ctypes.c_void_p, _dp]
+    lib.orc_set_h.argtypes = [ctypes.c_void_p, _dp]
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -157,6 +161,18 @@ def source(d: int, tau: float, u, F) -> np.ndarray:
     return out[: (9 if d == 2 else 19)].copy()
 
 
+def feq5(phi: float, mu: float, u, gamma_h: float) -> np.ndarray:
+    """Equilibrium of the D2Q5 convection-diffusion populations."""
+    u2 = np.zeros(2)
+    u2[: len(u)] = u
+    out = np.zeros(5)
+    _load().orc_feq5(float(phi), float(mu), _ptr(u2), float(gamma_h), _ptr(out))
+    return out
+
+
+D2Q5 = (np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1]]), np.array([1 / 3, 1 / 6, 1 / 6, 1 / 6, 1 / 6]))
+
+
 def ch_advect(phi, u, dt: float, mode: int = 0) -> np.ndarray:
     phi = _f64(phi)
     u = _f64(u)
@@ -178,11 +194,12 @@ def ch_diffuse(h, phi, dt, gamma, a, b, kappa, cd_Q=1.0) -> np.ndarray:
 
 
 def make_params(a=-0.1, b=0.1, kappa=0.1, tau=1.0, gamma=1.0, N=0.3, Q=2.5, cd_Q=1.0, m=1,
-                force_form=1, advection=0, g=(0.0, 0.0, 0.0)) -> OrcParams:
+                force_form=1, advection=0, g=(0.0, 0.0, 0.0), cd_model=0, tau_phi=1.0) -> OrcParams:
     p = OrcParams()
     p.a, p.b, p.kappa, p.tau, p.gamma = a, b, kappa, tau, gamma
     p.N, p.Q, p.cd_Q = N, Q, cd_Q
     p.m, p.force_form, p.advection = int(m), int(force_form), int(advection)
+    p.cd_model, p.tau_phi = int(cd_model), float(tau_phi)
     for k in range(3):
         p.g[k] = g[k] if k < len(g) else 0.0
     return p
@@ -228,6 +245,18 @@ class Oracle:
         phi = np.zeros(self.shape)
         _load().orc_get_state(self._ctx, _ptr(f), _ptr(phi))
         return f, phi
+
+    def h_state(self):
+        """D2Q5 populations (5, *shape) of the convection-diffusion model."""
+        h = np.zeros((5,) + self.shape)
+        if _load().orc_get_h(self._ctx, _ptr(h)) != 0:
+            raise ValueError("no D2Q5 populations (cd_model = 0)")
+        return h
+
+    def set_h(self, h):
+        h = _f64(h).reshape((5,) + self.shape)
+        if _load().orc_set_h(self._ctx, _ptr(h)) != 0:
+            raise ValueError("no D2Q5 populations (cd_model = 0)")
 
     def step(self, nsteps: int = 1):
         if _load().orc_step(self._ctx, int(nsteps)) != 0:
