@@ -129,6 +129,26 @@ hlb_status hlb_workspace_size(int lattice, int storage, int nx, int ny, int nz, 
 hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz,
                       const hlb_params *p, void *workspace, size_t bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): creates a
+ * context exactly like hlb_create, but its workspace is a static device
+ * array of the library of HLB_NOALLOC_MAX_BYTES bytes instead of caller
+ * memory.  Allocates no device memory; each GPU the library runs on holds
+ * its own array from the first call on it until the process ends.
+ * Lattices whose hlb_workspace_size exceeds HLB_NOALLOC_MAX_BYTES (64 MiB:
+ * e.g. D2Q9 up to 512 x 512 in float storage or 256 x 256 in double, D3Q19
+ * up to 64^3 in float) are rejected with HLB_ESHAPE.  One such context per
+ * device at a time: while one is alive, another hlb_create_noalloc on the
+ * same device returns HLB_ESTATE; hlb_destroy frees the array again.  The
+ * array keeps the last context's contents, which the next context never
+ * reads before writing (initialise it with hlb_init_fields, hlb_set_state
+ * or hlb_load).  Calls from several threads that overlap on one device's
+ * array race, like any use of one context from several threads.  The
+ * other calls of the context are the ones above, unchanged. */
+#define HLB_NOALLOC_MAX_BYTES (64u << 20)
+hlb_status hlb_create_noalloc(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz,
+                              const hlb_params *p, void *stream);
+
 /* Replaces the parameters between steps (revalidated as hlb_check_params). */
 hlb_status hlb_set_params(hlb_ctx *ctx, const hlb_params *p);
 

@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhlb.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = [os.path.join(CSRC, "hlb_api.hip"), os.path.join(CSRC, "sur_api.hip")]
+SOURCES = [os.path.join(CSRC, "hlb_api.hip"), os.path.join(CSRC, "hlb_noalloc.hip"), os.path.join(CSRC, "sur_api.hip")]
 HEADERS = [os.path.join(CSRC, h) for h in ("kernels.hpp", "lattice.hpp", "sur_kernels.hpp")] + [
     os.path.join(ROOT, "include", h) for h in ("hlb.h", "sur.h")]
 

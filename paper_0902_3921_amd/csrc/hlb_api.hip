@@ -248,6 +248,7 @@ struct hlb_ctx {
   std::string names[2];
   ChPlan plan;
   bool plan_user;  // plan set through hlb_set_plan
+  bool noalloc;    // the workspace is the library's static array (hlb_create_noalloc)
 };
 
 namespace {
@@ -704,8 +705,13 @@ hlb_status hlb_workspace_size(int lattice, int storage, int nx, int ny, int nz, 
   return HLB_OK;
 }
 
-hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz, const hlb_params *p,
-                      void *workspace, size_t bytes, void *stream) {
+}  // extern "C"
+
+// Creates a context over `workspace`; `static_ws` marks the library's own
+// static array (hlb_create_noalloc), which the runtime does not list as an
+// allocation, so the pointer check is skipped for it.
+hlb_status hlb_internal_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz, const hlb_params *p,
+                               void *workspace, size_t bytes, void *stream, bool static_ws) {
   std::string msg;
   if (!out) return fail(nullptr, HLB_EINVAL, "out is NULL");
   *out = nullptr;
@@ -721,10 +727,12 @@ hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, i
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail(nullptr, HLB_EHIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
-  hipPointerAttribute_t attr;
-  e = hipPointerGetAttributes(&attr, workspace);
-  if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
-    return fail(nullptr, HLB_EINVAL, "workspace is not device memory");
+  if (!static_ws) {
+    hipPointerAttribute_t attr;
+    e = hipPointerGetAttributes(&attr, workspace);
+    if (e != hipSuccess || attr.type != hipMemoryTypeDevice)
+      return fail(nullptr, HLB_EINVAL, "workspace is not device memory");
+  }
   hlb_ctx *c = new (std::nothrow) hlb_ctx();
   if (!c) return fail(nullptr, HLB_EINVAL, "out of host memory");
   c->lattice = lattice;
@@ -750,8 +758,19 @@ hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, i
   c->names[1] = kernel_names(lattice, storage, 1);
   c->plan = default_plan(c);
   c->plan_user = false;
+  c->noalloc = static_ws;
   *out = c;
   return HLB_OK;
+}
+
+void hlb_internal_set_create_error(const std::string &msg) { g_create_error = msg; }
+void hlb_internal_release_noalloc(const hlb_ctx *c);
+
+extern "C" {
+
+hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz, const hlb_params *p,
+                      void *workspace, size_t bytes, void *stream) {
+  return hlb_internal_create(out, lattice, storage, nx, ny, nz, p, workspace, bytes, stream, false);
 }
 
 hlb_status hlb_set_params(hlb_ctx *c, const hlb_params *p) {
@@ -1257,6 +1276,7 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
 const char *hlb_last_error(const hlb_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 hlb_status hlb_destroy(hlb_ctx *c) {
+  if (c && c->noalloc) hlb_internal_release_noalloc(c);
   delete c;
   return HLB_OK;
 }

@@ -28,7 +28,7 @@ EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_
            "hlb_set_params", "hlb_get_params", "hlb_init_fields", "hlb_set_state", "hlb_get_state",
            "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name", "hlb_time_kernels",
            "hlb_set_plan", "hlb_get_plan", "hlb_autotune", "hlb_last_error", "hlb_destroy", "hlb_version",
-           "hlb_checkpoint_size", "hlb_save", "hlb_load",
+           "hlb_checkpoint_size", "hlb_save", "hlb_load", "hlb_create_noalloc",
            "hlb_batch_workspace_size", "hlb_batch_create", "hlb_batch_info", "hlb_batch_init_fields",
            "hlb_batch_step", "hlb_batch_step_timed", "hlb_batch_set_plan", "hlb_batch_get_plan", "hlb_batch_autotune",
            "hlb_batch_get_fields", "hlb_batch_reduce", "hlb_batch_last_error",
@@ -81,6 +81,7 @@ def load():
         "hlb_workspace_size": (st, [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_size_t)]),
         "hlb_create": (st, [ctypes.POINTER(_vp)] + [ctypes.c_int] * 5
                        + [ctypes.POINTER(Params), _vp, ctypes.c_size_t, _vp]),
+        "hlb_create_noalloc": (st, [ctypes.POINTER(_vp)] + [ctypes.c_int] * 5 + [ctypes.POINTER(Params), _vp]),
         "hlb_set_params": (st, [_vp, ctypes.POINTER(Params)]),
         "hlb_get_params": (st, [_vp, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int)]),
         "hlb_init_fields": (st, [_vp, _dp, _dp, _dp]),
@@ -203,7 +204,7 @@ class Sim:
     of ``fd_substeps``).
     """
 
-    def __init__(self, shape, storage="f32", stream=None, **kw):
+    def __init__(self, shape, storage="f32", stream=None, noalloc=False, **kw):
         import torch
 
         if not torch.cuda.is_available():
@@ -216,14 +217,19 @@ class Sim:
         self.storage = _STORAGE[storage]
         nx, ny, nz = _dims(self.shape)
         self.ns = nx * ny * nz
-        nbytes = workspace_size(self.lattice, self.storage, nx, ny, nz)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self._params = params(**kw)
         ctx = _vp()
-        _check(self.lib.hlb_create(ctypes.byref(ctx), self.lattice, self.storage, nx, ny, nz,
-                                   ctypes.byref(self._params), ctypes.c_void_p(self.workspace.data_ptr()),
-                                   nbytes, ctypes.c_void_p(self.stream.cuda_stream)))
+        if noalloc:  # hlb_create_noalloc: the library's static workspace
+            self.workspace = None
+            _check(self.lib.hlb_create_noalloc(ctypes.byref(ctx), self.lattice, self.storage, nx, ny, nz,
+                                               ctypes.byref(self._params), ctypes.c_void_p(self.stream.cuda_stream)))
+        else:
+            nbytes = workspace_size(self.lattice, self.storage, nx, ny, nz)
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            _check(self.lib.hlb_create(ctypes.byref(ctx), self.lattice, self.storage, nx, ny, nz,
+                                       ctypes.byref(self._params), ctypes.c_void_p(self.workspace.data_ptr()),
+                                       nbytes, ctypes.c_void_p(self.stream.cuda_stream)))
         self.ctx = ctx
 
     # -- lifetime
