@@ -174,7 +174,7 @@ def run_gpu(name, steps, warmup, plan=None, profile_mode=False, variants=True):
     # kernel durations: event pairs around `reps` repetitions each; the
     # substep launches as they run in a step (after a collide-and-stream
     # launch), the first launch scaled from its back-to-back share
-    reps = max(20, min(200, steps // 10))
+    reps = 20 if profile_mode else max(20, min(200, steps // 10))
     us_lb, us_first_b2b, us_ch_b2b, us_ch_step = sim.time_kernels(reps)
     us_first = us_first_b2b * us_ch_step / us_ch_b2b
     host_io = None
