@@ -51,6 +51,9 @@
  *     Gamma = Gamma_h (tau_phi - 1/2), so Gamma_h = Gamma / (tau_phi - 1/2).
  */
 #include <math.h>
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
 #include <stdlib.h>
 #include <string.h>
 #ifdef _OPENMP
@@ -805,6 +808,63 @@ int orc_reduce(const orc_ctx *c, double *out) {
   out[7] = finite;
   free(n);
   free(u);
+  return 0;
+}
+
+/* Bulk quantities of a drop for Laplace's law (Sec. 2, Eq. surftens):
+ * over the sites whose minimum-image distance from `centre` (x, y[, z]) is
+ * below r_in (the inside) and above r_out (the outside), the mean density,
+ * the mean phi and the mean bulk pressure of Eq. diagpress without its
+ * gradient terms, p0 = n c_s^2 + a phi^2 / 2 + 3 b phi^4 / 4; and the
+ * equimolar radius, from the volume V = (sum phi - phi_out N) /
+ * (phi_in - phi_out) of the phase with phi = phi_in: R = sqrt(V / pi) in
+ * 2D, (3 V / (4 pi))^(1/3) in 3D.
+ * out[0..2] = p, phi, n inside; out[3..5] = the same outside;
+ * out[6] = sum phi; out[7] = R; out[8], out[9] = the site counts. */
+int orc_drop_stats(const orc_ctx *c, const double *centre, double r_in, double r_out, double *out) {
+  const grid *g = &c->g;
+  const orc_params *p = &c->p;
+  long ns = g->ns, idx;
+  int k;
+  double *n = (double *)malloc(sizeof(double) * ns);
+  double s_in[3] = {0, 0, 0}, s_out[3] = {0, 0, 0}, phisum = 0.0, c_in = 0.0, c_out = 0.0, V;
+  orc_fields(c, n, NULL, NULL, NULL);
+  for (idx = 0; idx < ns; idx++) {
+    int xyz[3];
+    double r2 = 0.0, ph = c->phi[idx], p0;
+    xyz[0] = (int)(idx % g->nx);
+    xyz[1] = (int)((idx / g->nx) % g->ny);
+    xyz[2] = (int)(idx / ((long)g->nx * g->ny));
+    for (k = 0; k < g->d; k++) {
+      int len = k == 0 ? g->nx : (k == 1 ? g->ny : g->nz);
+      double dx = xyz[k] - centre[k];
+      dx -= len * floor(dx / len + 0.5); /* minimum image */
+      r2 += dx * dx;
+    }
+    p0 = n[idx] * CS2 + p->a * ph * ph / 2.0 + 3.0 * p->b * ph * ph * ph * ph / 4.0;
+    phisum += ph;
+    if (r2 < r_in * r_in) {
+      s_in[0] += p0;
+      s_in[1] += ph;
+      s_in[2] += n[idx];
+      c_in += 1.0;
+    } else if (r2 > r_out * r_out) {
+      s_out[0] += p0;
+      s_out[1] += ph;
+      s_out[2] += n[idx];
+      c_out += 1.0;
+    }
+  }
+  for (k = 0; k < 3; k++) {
+    out[k] = c_in > 0 ? s_in[k] / c_in : 0.0;
+    out[3 + k] = c_out > 0 ? s_out[k] / c_out : 0.0;
+  }
+  out[6] = phisum;
+  V = (phisum - out[4] * (double)ns) / (out[1] - out[4]);
+  out[7] = g->d == 2 ? sqrt(V / M_PI) : cbrt(3.0 * V / (4.0 * M_PI));
+  out[8] = c_in;
+  out[9] = c_out;
+  free(n);
   return 0;
 }
 

@@ -83,6 +83,7 @@ def _load():
     lib.orc_feq5.argtypes = [ctypes.c_double, ctypes.c_double, _dp, ctypes.c_double, _dp]
     lib.orc_get_h.argtypes = [ctypes.c_void_p, _dp]
     lib.orc_set_h.argtypes = [ctypes.c_void_p, _dp]
+    lib.orc_drop_stats.argtypes = [ctypes.c_void_p, _dp, ctypes.c_double, ctypes.c_double, _dp]
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_set_threads.argtypes = [ctypes.c_int]
     _lib = lib
@@ -274,6 +275,18 @@ class Oracle:
         mu = np.zeros(self.shape)
         _load().orc_fields(self._ctx, _ptr(n), _ptr(u), _ptr(phi), _ptr(mu))
         return {"n": n, "u": u, "phi": phi, "mu": mu}
+
+    def drop_stats(self, centre, r_in, r_out):
+        """Bulk pressure, phi and n inside (distance < r_in) and outside
+        (distance > r_out) a drop centred at ``centre`` (x, y[, z]), the sum
+        of phi and the equimolar radius (see orc_drop_stats)."""
+        c = np.zeros(3)
+        c[: len(centre)] = centre
+        out = np.zeros(10)
+        _load().orc_drop_stats(self._ctx, _ptr(c), float(r_in), float(r_out), _ptr(out))
+        return {"p_in": out[0], "phi_in": out[1], "n_in": out[2], "p_out": out[3], "phi_out": out[4],
+                "n_out": out[5], "phi_sum": out[6], "radius": out[7], "count_in": int(out[8]),
+                "count_out": int(out[9]), "dp": out[0] - out[3]}
 
     def reduce(self):
         out = np.zeros(8)

@@ -344,3 +344,41 @@ def test_table1_spurious_velocity_tau1():
     sc.step(2500)
     ratio = sc.reduce()["umax"] / CS / oc
     assert 5 < ratio < 15
+
+
+@pytest.mark.parametrize("shape,centre", [((48, 40), (13.0, 30.0)), ((48, 40), (1.0, 2.0)),
+                                          ((20, 24, 22), (10.0, 3.0, 18.0))])
+def test_drop_stats_of_a_hand_built_drop(shape, centre):
+    """The drop statistics behind Laplace's law, on a state built by the test:
+    phi = +1 within distance R0 of the centre (minimum image, so the drop may
+    straddle the periodic boundary) and -1 outside, n = 1.1 inside and 0.9
+    outside, at rest.  The inner and outer means are then exact, the bulk
+    pressure is n c_s^2 + a/2 + 3b/4 (Eq. diagpress, phi^2 = phi^4 = 1), and
+    the equimolar radius is the radius of the disc (sphere) holding exactly
+    the sites with phi = +1."""
+    d = len(shape)
+    R0 = 7.3
+    grids = np.meshgrid(*[np.arange(n, dtype=float) for n in shape], indexing="ij")
+    r2 = np.zeros(shape)
+    for gr, c, n in zip(grids, reversed(centre), shape):
+        dx = gr - c
+        dx -= n * np.floor(dx / n + 0.5)
+        r2 += dx * dx
+    inside = r2 < R0 * R0
+    phi = np.where(inside, 1.0, -1.0)
+    n = np.where(inside, 1.1, 0.9)
+    _, w = orc.lattice(d)
+    f = w.reshape((-1,) + (1,) * d) * n
+    o = orc.Oracle(shape, **BASE, N=0.3, Q=2.5, m=1)
+    o.set_state(f, phi)
+    st = o.drop_stats(centre, 5.0, 11.0)
+    a, b = BASE["a"], BASE["b"]
+    assert st["p_in"] == pytest.approx(1.1 / 3 + a / 2 + 3 * b / 4, rel=1e-14)
+    assert st["p_out"] == pytest.approx(0.9 / 3 + a / 2 + 3 * b / 4, rel=1e-14)
+    assert st["phi_in"] == 1.0 and st["phi_out"] == -1.0
+    assert st["n_in"] == pytest.approx(1.1, rel=1e-14) and st["n_out"] == pytest.approx(0.9, rel=1e-14)
+    nin = int(inside.sum())
+    expect_r = np.sqrt(nin / np.pi) if d == 2 else np.cbrt(3 * nin / (4 * np.pi))
+    assert st["radius"] == pytest.approx(expect_r, rel=1e-13)
+    assert st["count_in"] == int((r2 < 25.0).sum()) and st["count_out"] == int((r2 > 121.0).sum())
+    assert st["phi_sum"] == pytest.approx(phi.sum(), abs=1e-9)
