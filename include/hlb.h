@@ -88,9 +88,23 @@ typedef struct {
   int force_form;      /* 1 = expanded form (default), 0 = -phi grad_D(mu) */
   int advection;       /* 0 = the paper's non-conservative upwind step (default),
                           1 = conservative upwind face fluxes */
-  int reserved;        /* must be 0 */
+  int cd_model;        /* how phi is advanced: 0 = the finite differences of
+                          Sec. 2.3 (default); 1 = the D2Q5 lattice Boltzmann
+                          alternative that Sec. 2 names (D2Q9 contexts only):
+                          populations h_i on c_0 = 0 and the four axis vectors,
+                          weights 1/3 and 1/6, h_i^eq = w_i (Gamma_h mu +
+                          phi c_i.u*) / c_s^2 (i > 0), h_0^eq = phi - sum of
+                          the others, relaxation 1/tau_phi, Gamma_h =
+                          Gamma / (tau_phi - 1/2), mu with the cd_Q Laplacian;
+                          phi = sum h_i.  No substeps (fd_substeps 0 or 1), so
+                          Gamma (kappa s^2 + a_eff s) <= 2 is required
+                          (HLB_EUNSTABLE otherwise).  Fixed at creation: it sets
+                          the workspace layout (hlb_workspace_size_params) */
   double g_ext[3];     /* uniform body acceleration: n*g_ext is added to F (Sec. 3) */
   double rho0;         /* reference density of the stored deviations; > 0 */
+  double tau_phi;      /* relaxation time of the D2Q5 populations (cd_model 1);
+                          0 = the smallest value >= 1 with Gamma_h (a_eff + kappa s)
+                          <= 0.45, else > 1/2 */
 } hlb_params;
 
 /* Global diagnostics at the current time (all sums in double precision,
@@ -108,7 +122,8 @@ typedef struct {
 
 /* Fills p with a = -0.1, b = 0.1, kappa = 0.1, tau = 1, Gamma = 1, the paper's
  * optimal stencil N = 0.3, Q = 2.5 (Sec. 3, Table I), cd_Q = 1, m = 0
- * (automatic), expanded force, paper advection, g_ext = 0, rho0 = 1. */
+ * (automatic), expanded force, paper advection, the finite-difference
+ * convection-diffusion model, g_ext = 0, rho0 = 1, tau_phi = 0. */
 hlb_status hlb_params_default(hlb_params *p);
 
 /* Checks p for lattice `lattice` without touching the device and writes the
@@ -122,8 +137,14 @@ hlb_status hlb_check_params(int lattice, const hlb_params *p, int *m_out);
  * otherwise HLB_ESHAPE.  Host only. */
 hlb_status hlb_workspace_size(int lattice, int storage, int nx, int ny, int nz, size_t *bytes);
 
+/* The same for a context created with parameters p (NULL: the defaults):
+ * the D2Q5 convection-diffusion model (cd_model 1) adds two buffers of its
+ * five populations.  Host only. */
+hlb_status hlb_workspace_size_params(int lattice, int storage, int nx, int ny, int nz, const hlb_params *p,
+                                     size_t *bytes);
+
 /* Creates a context on the current HIP device.  `workspace` is a device
- * pointer to `bytes` bytes (>= hlb_workspace_size), `stream` a hipStream_t
+ * pointer to `bytes` bytes (>= hlb_workspace_size_params), `stream` a hipStream_t
  * or NULL.  The state is undefined until hlb_init_fields or hlb_set_state.
  * On failure *out is NULL. */
 hlb_status hlb_create(hlb_ctx **out, int lattice, int storage, int nx, int ny, int nz,
@@ -163,7 +184,8 @@ hlb_status hlb_init_fields(hlb_ctx *ctx, const double *phi, const double *n, con
 
 /* Sets the raw state: populations f[q*ns] (after streaming, before the
  * collision of the next step) and phi[ns], host double arrays.  Resets the
- * step counter.  Synchronises. */
+ * step counter.  Synchronises.  HLB_EINVAL with the D2Q5 model, whose state
+ * also holds its populations (use hlb_init_fields or hlb_load). */
 hlb_status hlb_set_state(hlb_ctx *ctx, const double *f, const double *phi);
 
 /* Reads the raw state into host arrays f[q*ns] and phi[ns] (either may be
@@ -186,6 +208,25 @@ hlb_status hlb_get_fields(hlb_ctx *ctx, double *n, double *u, double *phi, doubl
  * Synchronises. */
 hlb_status hlb_reduce(hlb_ctx *ctx, hlb_stats *out);
 
+/* Bulk quantities of a drop for Laplace's law, Delta p = sigma / R in 2D and
+ * 2 sigma / R in 3D, with sigma of Sec. 2, Eq. surftens.  Over the sites
+ * whose minimum-image distance from centre (x, y[, z]; centre[2] is ignored
+ * for D2Q9) is below r_in ("in") or above r_out ("out"), the means of the
+ * bulk pressure of Eq. diagpress without its gradient terms,
+ * p0 = n c_s^2 + a phi^2 / 2 + 3 b phi^4 / 4, of phi and of n = sum f_i;
+ * dp = p_in - p_out; the sum of phi; and the equimolar radius: the volume
+ * V = (sum phi - phi_out ns) / (phi_in - phi_out) of the phase of phi_in,
+ * R = sqrt(V / pi) (2D) or (3 V / (4 pi))^(1/3) (3D).  Sums in double
+ * precision on the device in a fixed order.  HLB_EINVAL unless
+ * 0 <= r_in <= r_out and both regions hold a site.  Synchronises. */
+typedef struct {
+  double p_in, phi_in, n_in;
+  double p_out, phi_out, n_out;
+  double dp, phi_sum, radius;
+  long long count_in, count_out;
+} hlb_drop;
+hlb_status hlb_drop_stats(hlb_ctx *ctx, const double centre[3], double r_in, double r_out, hlb_drop *out);
+
 /* Runs nsteps timesteps like hlb_step, recording HIP events around every
  * kernel launch on the context's stream, synchronises, and writes the
  * summed kernel time in milliseconds per kernel class:
@@ -204,6 +245,12 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
  *                     substeps (1, 2, 3 or 5) of plan[2] x plan[2] tiles
  *                     (16, 32, 48 or 64) in LDS, halo 3 per substep, when the
  *                     staged tile fits a CU's 160 KiB of LDS;
+ *                 3 = fused tiles like kind 2 (edge 32, 48 or 64, plan[3]
+ *                     = 512 or 1024 threads, 0 = 1024) in which every thread
+ *                     keeps the same staged vectors in registers for the
+ *                     whole launch (at most 3 per thread) and each site's
+ *                     advection half-step is precomputed as five
+ *                     coefficients;
  *   plan[1] fuse: substeps per launch, 1..5 (D2Q9), 1 (D3Q19);
  *   plan[2] bw:   D2Q9: columns per block, 64, 128 or 256 (256 with
  *                 HLB_F32_SHIFTED only), bw - 6*fuse >= 16;
@@ -211,7 +258,8 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
  *                 columns: 256 (16x32 columns), 512 (32x32) or 1024 (64x32,
  *                 HLB_F32_SHIFTED and cd_Q = 1 only);
  *   plan[3] seg:  kind 1: rows (D2Q9) or planes (D3Q19) per block, >= 1;
- *                 kind 2: threads per block, 256, 512 or 1024 (0 = 256).
+ *                 kind 2: threads per block, 256, 512 or 1024 (0 = 256);
+ *                 kind 3: 512 or 1024 (0 = 1024).
  * hlb_create picks a plan from the lattice size; hlb_set_plan overrides it
  * (HLB_EINVAL if the plan cannot run this context).  hlb_set_params keeps a
  * user plan while it stays valid. */

@@ -58,8 +58,18 @@ constexpr size_t fused_tile_lds(size_t es, int M, int TO) {
   return 4 * rows * pitch * es;
 }
 
+// The fixed-mapping fused tile (k_ch_tile2): LDS of its two arrays, and the
+// vectors of the staged box per thread, which stay in registers (at most 3).
+constexpr size_t fused_tile2_lds(size_t es, int M, int TO) { return fused_tile_lds(es, M, TO) / 2; }
+constexpr int fused_tile2_items(size_t es, int M, int TO, int NTH) {
+  const int V = 16 / (int)es, H = 3 * M, HA = (H + V - 1) / V * V;
+  const int rows = TO + 2 * H, nq = (TO + 2 * HA) / V;
+  return (rows * nq + NTH - 1) / NTH;
+}
+constexpr int kTile2MaxItems = 3;
+
 struct Layout {
-  size_t g[2], phi[2], u, io, part, out, total;
+  size_t g[2], phi[2], u, io, part, out, h[2], total;  // h: D2Q5 populations (cd_model 1), else 0
   int nblk_reduce;
 };
 
@@ -97,7 +107,7 @@ hlb_status check_shape(int lattice, int storage, int nx, int ny, int nz, std::st
   return HLB_OK;
 }
 
-Layout make_layout(int lattice, int storage, int nx, int ny, int nz) {
+Layout make_layout(int lattice, int storage, int nx, int ny, int nz, bool cd5 = false) {
   Layout L{};
   const size_t ns = (size_t)nx * ny * nz;
   const size_t es = storage == HLB_F64 ? 8 : 4;
@@ -116,10 +126,14 @@ Layout make_layout(int lattice, int storage, int nx, int ny, int nz) {
   L.io = off;  // double precision staging: [n | u (d) | phi | mu]
   off = align_up(off + (3 + d) * ns * 8);
   L.nblk_reduce = reduce_blocks(lattice, storage, nx, ny, nz);
-  L.part = off;
-  off = align_up(off + (size_t)L.nblk_reduce * 8 * 8);
+  L.part = off;  // 16 doubles per block (the reduction uses 8, the drop statistics 9)
+  off = align_up(off + (size_t)L.nblk_reduce * 16 * 8);
   L.out = off;
-  off = align_up(off + 8 * 8);
+  off = align_up(off + 16 * 8);
+  for (int k = 0; k < 2 && cd5; k++) {
+    L.h[k] = off;
+    off = align_up(off + 5 * ns * es);
+  }
   L.total = off;
   return L;
 }
@@ -189,8 +203,16 @@ hlb_status validate(int lattice, const hlb_params *p, int *m_out, std::string *m
     *msg = "advection must be 0 or 1";
     return HLB_EINVAL;
   }
-  if (p->fd_substeps < 0 || p->reserved != 0) {
-    *msg = "fd_substeps must be >= 0 and reserved 0";
+  if (p->fd_substeps < 0) {
+    *msg = "fd_substeps must be >= 0";
+    return HLB_EINVAL;
+  }
+  if (p->cd_model != 0 && p->cd_model != 1) {
+    *msg = "cd_model must be 0 (finite differences) or 1 (D2Q5 lattice Boltzmann)";
+    return HLB_EINVAL;
+  }
+  if (!std::isfinite(p->tau_phi) || (p->tau_phi != 0.0 && !(p->tau_phi > 0.5))) {
+    *msg = "tau_phi must be 0 (automatic) or > 1/2";
     return HLB_EINVAL;
   }
   const int d = lattice_d(lattice);
@@ -206,6 +228,27 @@ hlb_status validate(int lattice, const hlb_params *p, int *m_out, std::string *m
   // checkerboard bound of the explicit diffusion step, Gamma dt (kappa s^2 + a_eff s) <= 2
   const double a_eff = p->a < 0 ? -2.0 * p->a : p->a + 3.0 * p->b;
   const double rate = p->gamma * (p->kappa * smax * smax + a_eff * smax);
+  if (p->cd_model == 1) {
+    // the D2Q5 model has no substeps; at tau_phi = 1 its step is the explicit
+    // Euler step of the convection-diffusion equation, so the bound is m = 1's
+    if (d != 2) {
+      *msg = "the D2Q5 convection-diffusion model needs the D2Q9 lattice";
+      return HLB_EINVAL;
+    }
+    if (p->fd_substeps > 1) {
+      *msg = "the D2Q5 convection-diffusion model has no substeps (fd_substeps 0 or 1)";
+      return HLB_EINVAL;
+    }
+    if (rate > 2.0 + 1e-12) {
+      char buf[200];
+      snprintf(buf, sizeof buf,
+               "the D2Q5 model advances phi by a whole LB step: Gamma (kappa s^2 + a_eff s) = %.4g exceeds 2", rate);
+      *msg = buf;
+      return HLB_EUNSTABLE;
+    }
+    if (m_out) *m_out = 1;
+    return HLB_OK;
+  }
   int m = p->fd_substeps;
   if (m == 0) {
     m = std::max(1, (int)std::ceil(rate / 1.8 - 1e-12));
@@ -220,15 +263,28 @@ hlb_status validate(int lattice, const hlb_params *p, int *m_out, std::string *m
   return HLB_OK;
 }
 
+// tau_phi of the D2Q5 model: the given one, or the smallest value >= 1 that
+// keeps the rest population of the equilibrium of the checkerboard mode
+// non-negative with a margin, Gamma_h (a_eff + kappa s) <= 0.45.
+double resolve_tau_phi(int d, const hlb_params &p) {
+  if (p.tau_phi != 0.0) return p.tau_phi;
+  double smax = 0.0;
+  lap_symbol_range(d, p.cd_Q, &smax);
+  const double a_eff = p.a < 0 ? -2.0 * p.a : p.a + 3.0 * p.b;
+  const double lam = a_eff + p.kappa * smax;
+  return std::max(1.0, 0.5 + p.gamma * lam / 0.45);
+}
+
 }  // namespace
 
 // Execution plan of the convection-diffusion substeps of a step.
 struct ChPlan {
   int kind;  // 0: one tiled launch per substep; 1: marching launches (y in D2Q9 with cd_Q = 1,
-             // z in D3Q19); 2: fused LDS tiles (D2Q9)
+             // z in D3Q19); 2: fused LDS tiles (D2Q9); 3: fused tiles with a fixed
+             // vector-to-thread mapping (D2Q9)
   int fuse;  // substeps per launch, 1..5 (1 in D3Q19)
-  int bw;    // kind 1: columns per block (D2Q9) or threads per block (D3Q19); kind 2: tile edge
-  int seg;   // kind 1: rows or planes per block; kind 2: threads per block (0 means 256)
+  int bw;    // kind 1: columns per block (D2Q9) or threads per block (D3Q19); kinds 2, 3: tile edge
+  int seg;   // kind 1: rows or planes per block; kinds 2, 3: threads per block (0 means 256 or 1024)
 };
 
 struct hlb_ctx {
@@ -241,7 +297,7 @@ struct hlb_ctx {
   char *ws;
   size_t ws_bytes;
   Layout lay;
-  int gcur, phicur;
+  int gcur, phicur, hcur;
   long long step;
   bool error_state;
   std::string err;
@@ -300,6 +356,11 @@ KParams make_kparams(int d, int nx, int ny, int nz, const hlb_params &p, int m) 
   k.rho0 = p.rho0;
   k.force_form = p.force_form;
   k.advection = p.advection;
+  if (p.cd_model == 1) {
+    const double tp = resolve_tau_phi(d, p);
+    k.omega_h = 1.0 / tp;
+    k.gamma_h = p.gamma / (tp - 0.5);
+  }
   return k;
 }
 
@@ -324,6 +385,30 @@ struct Ops {
     T *gout = at<T>(c, c->lay.g[1 - c->gcur]);
     hipLaunchKernelGGL((k_lb<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k, gin, gout,
                        at<T>(c, c->lay.phi[c->phicur]), at<T>(c, c->lay.u));
+  }
+  // the D2Q5 convection-diffusion model: force + collide-and-stream of f and
+  // h in one launch, then phi = sum h
+  static void lb5(hlb_ctx *c, const KParams &k) {
+    if constexpr (L::D == 2) {
+      hipLaunchKernelGGL((k_lb5<T, LB0, LB1>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k,
+                         at<T>(c, c->lay.g[c->gcur]), at<T>(c, c->lay.g[1 - c->gcur]),
+                         at<T>(c, c->lay.phi[c->phicur]), at<T>(c, c->lay.h[c->hcur]),
+                         at<T>(c, c->lay.h[1 - c->hcur]));
+    }
+  }
+  static void phi5(hlb_ctx *c, const KParams &k, int hbuf, T *dst) {
+    if constexpr (L::D == 2) {
+      const unsigned nb = (unsigned)((c->ns + 255) / 256);
+      hipLaunchKernelGGL((k_phi5<T>), dim3(nb), dim3(256), 0, c->stream, k, at<T>(c, c->lay.h[hbuf]), dst);
+    }
+  }
+  static void init5(hlb_ctx *c, const KParams &k) {
+    if constexpr (L::D == 2) {
+      const unsigned nb = (unsigned)((c->ns + 255) / 256);
+      hipLaunchKernelGGL((k_init5<T>), dim3(nb), dim3(256), 0, c->stream, k, at<double>(c, c->lay.io),
+                         at<T>(c, c->lay.h[c->hcur]));
+      phi5(c, k, c->hcur, at<T>(c, c->lay.phi[c->phicur]));
+    }
   }
   static void ch(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
     if (c->p.cd_Q == 1.0)
@@ -423,6 +508,42 @@ struct Ops {
       default: tile1<5, TO>(c, k, src, dst); break;
     }
   }
+  // fixed-mapping fused tiles (kind 3): plan.bw the tile edge, plan.seg the threads
+  template <int M, int TO, int NTH>
+  static void tile2_launch(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
+    static_assert(fused_tile2_lds(sizeof(T), M, TO) == FusedTile2<T, M, TO, NTH>::LDS, "LDS formula");
+    static_assert(fused_tile2_items(sizeof(T), M, TO, NTH) == FusedTile2<T, M, TO, NTH>::K, "items formula");
+    if constexpr (fused_tile2_lds(sizeof(T), M, TO) <= kMaxLds &&
+                  fused_tile2_items(sizeof(T), M, TO, NTH) <= kTile2MaxItems) {
+      const dim3 grid(ceil_div(c->nx, TO), ceil_div(c->ny, TO));
+      const T *uu = at<T>(c, c->lay.u);
+      if (c->p.cd_Q != 1.0)
+        hipLaunchKernelGGL((k_ch_tile2<T, M, TO, NTH, true>), grid, dim3(NTH), 0, c->stream, k, src, uu, dst);
+      else
+        hipLaunchKernelGGL((k_ch_tile2<T, M, TO, NTH, false>), grid, dim3(NTH), 0, c->stream, k, src, uu, dst);
+    }
+  }
+  template <int M, int TO>
+  static void tile2_m(hlb_ctx *c, const KParams &k, const T *src, T *dst) {
+    if (c->plan.seg == 512) tile2_launch<M, TO, 512>(c, k, src, dst);
+    else tile2_launch<M, TO, 1024>(c, k, src, dst);
+  }
+  template <int TO>
+  static void tile2_to(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
+    switch (M) {
+      case 1: tile2_m<1, TO>(c, k, src, dst); break;
+      case 2: tile2_m<2, TO>(c, k, src, dst); break;
+      case 3: tile2_m<3, TO>(c, k, src, dst); break;
+      default: tile2_m<5, TO>(c, k, src, dst); break;
+    }
+  }
+  static void tile2(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
+    if constexpr (L::D == 2) {
+      if (c->plan.bw == 64) tile2_to<64>(c, k, M, src, dst);
+      else if (c->plan.bw == 48) tile2_to<48>(c, k, M, src, dst);
+      else tile2_to<32>(c, k, M, src, dst);
+    }
+  }
   // one fused-tile launch of M substeps
   static void tile(hlb_ctx *c, const KParams &k, int M, const T *src, T *dst) {
     if constexpr (L::D == 2) {
@@ -453,11 +574,12 @@ struct Ops {
         advance();
         done += M;
       }
-    } else if (c->plan.kind == 2) {
+    } else if (c->plan.kind == 2 || c->plan.kind == 3) {
       for (int done = 0; done < c->m && n < cap;) {
         int M = std::min(c->plan.fuse, c->m - done);
         if (M == 4) M = 3;  // instantiated: 1, 2, 3, 5
-        tile(c, k, M, src, dst);
+        if (c->plan.kind == 2) tile(c, k, M, src, dst);
+        else tile2(c, k, M, src, dst);
         advance();
         done += M;
       }
@@ -477,6 +599,13 @@ struct Ops {
   static void readout(hlb_ctx *c, const KParams &k) {
     hipLaunchKernelGGL((k_readout<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k,
                        at<T>(c, c->lay.g[c->gcur]), at<T>(c, c->lay.phi[c->phicur]), at<double>(c, c->lay.io));
+  }
+  static void drop_stats(hlb_ctx *c, const KParams &k, const double cen[3], double rin2, double rout2) {
+    hipLaunchKernelGGL((k_drop_stats<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k,
+                       at<T>(c, c->lay.g[c->gcur]), at<T>(c, c->lay.phi[c->phicur]), cen[0], cen[1], cen[2], rin2,
+                       rout2, at<double>(c, c->lay.part));
+    hipLaunchKernelGGL(k_drop_stats_final, dim3(1), dim3(256), 0, c->stream, c->lay.nblk_reduce,
+                       at<double>(c, c->lay.part), at<double>(c, c->lay.out));
   }
   static void reduce(hlb_ctx *c, const KParams &k) {
     hipLaunchKernelGGL((k_reduce<L, T, LB0, LB1, LB2>), tile_grid(c, TL::LB), dim3(256), 0, c->stream, k,
@@ -538,6 +667,20 @@ hlb_status usable(hlb_ctx *c) {
 
 // One timestep: force + collide-and-stream, then m convection-diffusion substeps.
 void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
+  if (c->p.cd_model == 1) {
+    dispatch(c, [&](auto ops) {
+      using T = typename decltype(ops)::Type;
+      if (ev) (void)hipEventRecord(ev[0], c->stream);
+      ops.lb5(c, k);
+      if (ev) (void)hipEventRecord(ev[1], c->stream);
+      ops.phi5(c, k, 1 - c->hcur, at<T>(c, c->lay.phi[c->phicur]));
+      if (ev) (void)hipEventRecord(ev[2], c->stream);
+    });
+    c->gcur = 1 - c->gcur;
+    c->hcur = 1 - c->hcur;
+    c->step++;
+    return;
+  }
   dispatch(c, [&](auto ops) {
     if (ev) (void)hipEventRecord(ev[0], c->stream);
     ops.lb(c, k);
@@ -555,6 +698,32 @@ void enqueue_step(hlb_ctx *c, const KParams &k, hipEvent_t *ev) {
 // Whether a plan can run this context.
 bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
   if (pl.kind == 0) return true;
+  if (pl.kind == 3) {
+    if (c->lattice != HLB_D2Q9) {
+      *why = "the fused tile kernel needs D2Q9";
+      return false;
+    }
+    if (pl.fuse < 1 || pl.fuse > 5 || pl.fuse == 4) {
+      *why = "fused tile: fuse must be 1, 2, 3 or 5";
+      return false;
+    }
+    if (pl.bw != 32 && pl.bw != 48 && pl.bw != 64) {
+      *why = "fixed-mapping fused tile: bw (tile edge) must be 32, 48 or 64";
+      return false;
+    }
+    if (pl.seg != 0 && pl.seg != 512 && pl.seg != 1024) {
+      *why = "fixed-mapping fused tile: seg (threads per block) must be 0 (1024), 512 or 1024";
+      return false;
+    }
+    const size_t es = c->storage == HLB_F64 ? 8 : 4;
+    const int M = std::min(pl.fuse, c->m) == 4 ? 3 : std::min(pl.fuse, c->m);
+    const int nth = pl.seg == 512 ? 512 : 1024;
+    if (fused_tile2_lds(es, M, pl.bw) > kMaxLds || fused_tile2_items(es, M, pl.bw, nth) > kTile2MaxItems) {
+      *why = "fixed-mapping fused tile: the staged box exceeds the LDS or 3 vectors per thread";
+      return false;
+    }
+    return true;
+  }
   if (pl.kind == 2) {
     if (c->lattice != HLB_D2Q9) {
       *why = "the fused tile kernel needs D2Q9";
@@ -579,7 +748,7 @@ bool plan_valid(const hlb_ctx *c, const ChPlan &pl, std::string *why) {
     return true;
   }
   if (pl.kind != 1) {
-    *why = "plan kind must be 0, 1 or 2";
+    *why = "plan kind must be 0, 1, 2 or 3";
     return false;
   }
   if (c->lattice == HLB_D2Q9 && c->p.cd_Q != 1.0) {
@@ -705,6 +874,17 @@ hlb_status hlb_workspace_size(int lattice, int storage, int nx, int ny, int nz, 
   return HLB_OK;
 }
 
+hlb_status hlb_workspace_size_params(int lattice, int storage, int nx, int ny, int nz, const hlb_params *p,
+                                     size_t *bytes) {
+  std::string msg;
+  if (!bytes) return fail(nullptr, HLB_EINVAL, "bytes is NULL");
+  hlb_status s = check_shape(lattice, storage, nx, ny, nz, &msg);
+  if (s != HLB_OK) return fail(nullptr, s, msg);
+  const bool cd5 = p && p->cd_model == 1;
+  *bytes = make_layout(lattice, storage, nx, ny, nz, cd5).total;
+  return HLB_OK;
+}
+
 }  // extern "C"
 
 // Creates a context over `workspace`; `static_ws` marks the library's own
@@ -720,7 +900,7 @@ hlb_status hlb_internal_create(hlb_ctx **out, int lattice, int storage, int nx, 
   int m = 0;
   s = validate(lattice, p, &m, &msg);
   if (s != HLB_OK) return fail(nullptr, s, msg);
-  const Layout lay = make_layout(lattice, storage, nx, ny, nz);
+  const Layout lay = make_layout(lattice, storage, nx, ny, nz, p->cd_model == 1);
   if (!workspace || bytes < lay.total) return fail(nullptr, HLB_ESHAPE, "workspace missing or too small");
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
     return fail(nullptr, HLB_EINVAL, "workspace must be 256-byte aligned");
@@ -752,6 +932,7 @@ hlb_status hlb_internal_create(hlb_ctx **out, int lattice, int storage, int nx, 
   c->lay = lay;
   c->gcur = 0;
   c->phicur = 0;
+  c->hcur = 0;
   c->step = 0;
   c->error_state = false;
   c->names[0] = kernel_names(lattice, storage, 0);
@@ -779,6 +960,8 @@ hlb_status hlb_set_params(hlb_ctx *c, const hlb_params *p) {
   int m = 0;
   hlb_status s = validate(c->lattice, p, &m, &msg);
   if (s != HLB_OK) return fail(c, s, msg);
+  if (p->cd_model != c->p.cd_model)
+    return fail(c, HLB_EINVAL, "cd_model is fixed when the context is created (it sets the workspace layout)");
   c->p = *p;
   c->m = m;
   std::string why;
@@ -814,8 +997,12 @@ hlb_status hlb_init_fields(hlb_ctx *c, const double *phi, const double *n, const
   if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
   c->gcur = 0;
   c->phicur = 0;
+  c->hcur = 0;
   const KParams k = kparams(c);
-  dispatch(c, [&](auto ops) { ops.init(c, k); });
+  dispatch(c, [&](auto ops) {
+    ops.init(c, k);
+    if (c->p.cd_model == 1) ops.init5(c, k);  // h = h^eq(phi0, mu0, u0), then phi = sum h
+  });
   hlb_status s = launch_check(c, "init kernel");
   if (s != HLB_OK) return s;
   s = sync(c);
@@ -828,6 +1015,8 @@ hlb_status hlb_init_fields(hlb_ctx *c, const double *phi, const double *n, const
 hlb_status hlb_set_state(hlb_ctx *c, const double *f, const double *phi) {
   if (!c) return HLB_EINVAL;
   if (!f || !phi) return fail(c, HLB_EINVAL, "f and phi must not be NULL");
+  if (c->p.cd_model == 1)
+    return fail(c, HLB_EINVAL, "the D2Q5 model's state includes its populations: use hlb_init_fields or hlb_load");
   const size_t ns = (size_t)c->ns;
   if (!finite_all(f, c->q * ns) || !finite_all(phi, ns))
     return fail(c, HLB_ENONFINITE, "non-finite value in the state");
@@ -902,7 +1091,8 @@ struct CkptHeader {
 };
 size_t ckpt_bytes(const hlb_ctx *c) {
   const size_t es = c->storage == HLB_F64 ? 8 : 4;
-  return sizeof(CkptHeader) + (size_t)(c->q + 1) * (size_t)c->ns * es;
+  const size_t nh = c->p.cd_model == 1 ? 5 : 0;  // D2Q5 populations
+  return sizeof(CkptHeader) + (size_t)(c->q + 1 + nh) * (size_t)c->ns * es;
 }
 }  // namespace
 
@@ -939,6 +1129,9 @@ hlb_status hlb_save(hlb_ctx *c, void *host, size_t bytes) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(dst + sizeof h + gbytes, c->ws + c->lay.phi[c->phicur], pbytes, hipMemcpyDeviceToHost,
                        c->stream);
+  if (e == hipSuccess && c->p.cd_model == 1)
+    e = hipMemcpyAsync(dst + sizeof h + gbytes + pbytes, c->ws + c->lay.h[c->hcur], 5 * pbytes,
+                       hipMemcpyDeviceToHost, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
   return sync(c);
 }
@@ -952,6 +1145,8 @@ hlb_status hlb_load(hlb_ctx *c, const void *host, size_t bytes) {
   if (h.lattice != c->lattice || h.storage != c->storage || h.nx != c->nx || h.ny != c->ny || h.nz != c->nz ||
       h.q != c->q)
     return fail(c, HLB_ESHAPE, "checkpoint of another lattice, storage or size");
+  if (h.p.cd_model != c->p.cd_model)
+    return fail(c, HLB_ESHAPE, "checkpoint of another convection-diffusion model (cd_model)");
   if (bytes < ckpt_bytes(c)) return fail(c, HLB_EINVAL, "checkpoint truncated");
   std::string msg;
   int m = 0;
@@ -963,11 +1158,15 @@ hlb_status hlb_load(hlb_ctx *c, const void *host, size_t bytes) {
   hipError_t e = hipMemcpyAsync(c->ws + c->lay.g[0], src + sizeof h, gbytes, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->ws + c->lay.phi[0], src + sizeof h + gbytes, pbytes, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess && c->p.cd_model == 1)
+    e = hipMemcpyAsync(c->ws + c->lay.h[0], src + sizeof h + gbytes + pbytes, 5 * pbytes, hipMemcpyHostToDevice,
+                       c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
   s = sync(c);
   if (s != HLB_OK) return s;
   c->gcur = 0;
   c->phicur = 0;
+  c->hcur = 0;
   c->step = h.step;
   c->error_state = false;
   s = hlb_set_params(c, &h.p);
@@ -1074,6 +1273,42 @@ hlb_status hlb_reduce(hlb_ctx *c, hlb_stats *out) {
   return HLB_OK;
 }
 
+hlb_status hlb_drop_stats(hlb_ctx *c, const double centre[3], double r_in, double r_out, hlb_drop *out) {
+  hlb_status s = usable(c);
+  if (s != HLB_OK) return s;
+  if (!centre || !out) return fail(c, HLB_EINVAL, "centre and out must not be NULL");
+  if (!std::isfinite(r_in) || !std::isfinite(r_out) || r_in < 0 || r_out < r_in)
+    return fail(c, HLB_EINVAL, "need 0 <= r_in <= r_out");
+  double cen[3] = {centre[0], centre[1], c->d == 3 ? centre[2] : 0.0};
+  for (double v : cen)
+    if (!std::isfinite(v)) return fail(c, HLB_EINVAL, "centre must be finite");
+  const KParams k = kparams(c);
+  dispatch(c, [&](auto ops) { ops.drop_stats(c, k, cen, r_in * r_in, r_out * r_out); });
+  s = launch_check(c, "drop statistics kernels");
+  if (s != HLB_OK) return s;
+  double r[9];
+  hipError_t e = hipMemcpyAsync(r, at<double>(c, c->lay.out), sizeof r, hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMemcpyAsync");
+  s = sync(c);
+  if (s != HLB_OK) return s;
+  std::memset(out, 0, sizeof *out);
+  out->count_in = (long long)r[0];
+  out->count_out = (long long)r[4];
+  if (r[0] < 1 || r[4] < 1) return fail(c, HLB_EINVAL, "no site inside r_in or none outside r_out");
+  out->p_in = r[1] / r[0];
+  out->phi_in = r[2] / r[0];
+  out->n_in = r[3] / r[0];
+  out->p_out = r[5] / r[4];
+  out->phi_out = r[6] / r[4];
+  out->n_out = r[7] / r[4];
+  out->phi_sum = r[8];
+  out->dp = out->p_in - out->p_out;
+  const double V = (r[8] - out->phi_out * (double)c->ns) / (out->phi_in - out->phi_out);
+  constexpr double pi = 3.14159265358979323846;
+  out->radius = c->d == 2 ? std::sqrt(V / pi) : std::cbrt(3.0 * V / (4.0 * pi));
+  return HLB_OK;
+}
+
 const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
   if (!c || cls < 0 || cls > 1) return "";
   hlb_ctx *mc = const_cast<hlb_ctx *>(c);
@@ -1089,13 +1324,23 @@ const char *hlb_kernel_name(const hlb_ctx *c, int cls) {
       t[1] = O::LB1;
       t[2] = O::LB2;
     });
-    snprintf(buf, sizeof buf, "hlb::k_lb<%s, %s, %d, %d, %d>", lat, ty, t[0], t[1], t[2]);
+    if (c->p.cd_model == 1)
+      snprintf(buf, sizeof buf, "hlb::k_lb5<%s, %d, %d>", ty, t[0], t[1]);
+    else
+      snprintf(buf, sizeof buf, "hlb::k_lb<%s, %s, %d, %d, %d>", lat, ty, t[0], t[1], t[2]);
+  } else if (c->p.cd_model == 1) {
+    snprintf(buf, sizeof buf, "hlb::k_phi5<%s>", ty);
   } else if (c->plan.kind == 2) {
     int M = std::min(c->plan.fuse, c->m);
     if (M == 4) M = 3;
     const int nth = c->plan.seg == 1024 ? 1024 : (c->plan.seg == 512 ? 512 : 256);
     snprintf(buf, sizeof buf, "hlb::k_ch_tile<%s, %d, %d, %s, %d, %s>", ty, M, c->plan.bw, flux, nth,
              c->p.cd_Q != 1.0 ? "true" : "false");
+  } else if (c->plan.kind == 3) {
+    int M = std::min(c->plan.fuse, c->m);
+    if (M == 4) M = 3;
+    snprintf(buf, sizeof buf, "hlb::k_ch_tile2<%s, %d, %d, %d, %s>", ty, M, c->plan.bw,
+             c->plan.seg == 512 ? 512 : 1024, c->p.cd_Q != 1.0 ? "true" : "false");
   } else if (c->plan.kind == 1 && c->lattice == HLB_D3Q19) {
     const int txi = c->plan.bw == 256 ? 16 : (c->plan.bw == 512 ? 32 : 64);
     snprintf(buf, sizeof buf, "hlb::%s<%s, %d, %d, %s>", c->p.cd_Q == 1.0 ? "k_ch_march3" : "k_ch_march3w", ty,
@@ -1138,6 +1383,13 @@ hlb_status hlb_time_kernels(hlb_ctx *c, int reps, double us[4]) {
       using T = typename decltype(ops)::Type;
       T *scratch = at<T>(c, c->lay.io);
       const T *phi = at<T>(c, c->lay.phi[c->phicur]);
+      if (c->p.cd_model == 1) {
+        // D2Q5: the combined collide-and-stream launch writes the spare f and h
+        // buffers; phi = sum h is formed from them into scratch
+        if (what == 0 || what == 3) ops.lb5(c, k);
+        if (what >= 1) ops.phi5(c, k, 1 - c->hcur, scratch);
+        return;
+      }
       if (what == 0 || what == 3) ops.lb(c, k);
       if (what == 1) ops.substeps(c, k, phi, scratch, scratch + c->ns, 1);
       if (what == 2 || what == 3) ops.substeps(c, k, phi, scratch, scratch + c->ns);
@@ -1189,6 +1441,10 @@ hlb_status hlb_get_plan(const hlb_ctx *c, int plan[4]) {
 hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   hlb_status s = usable(c);
   if (s != HLB_OK) return s;
+  if (c->p.cd_model == 1) {  // the D2Q5 model has no substep launches to plan
+    if (best_us) *best_us = 0.0;
+    return HLB_OK;
+  }
   // candidate plans, each timed on all the substeps of a step, reading the
   // current phi and writing scratch buffers, so the state is unchanged
   std::vector<ChPlan> cand;
@@ -1218,6 +1474,13 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
       for (int to : {16, 32, 48, 64})
         for (int nth : {256, 512, 1024}) {
           ChPlan pl{2, std::min(fuse, c->m == 4 ? 3 : c->m), to, nth};
+          std::string why;
+          if (fuse <= c->m && plan_valid(c, pl, &why)) cand.push_back(pl);
+        }
+    for (int fuse : {1, 2, 3, 5})
+      for (int to : {32, 48, 64})
+        for (int nth : {512, 1024}) {
+          ChPlan pl{3, std::min(fuse, c->m == 4 ? 3 : c->m), to, nth};
           std::string why;
           if (fuse <= c->m && plan_valid(c, pl, &why)) cand.push_back(pl);
         }
@@ -1773,6 +2036,9 @@ hlb_status hlb_batch_create(hlb_batch **out, int storage, int nsim, const int *n
   for (int i = 0; i < nsim; i++) {
     s = validate(HLB_D2Q9, &params[i], &ms[i], &msg);
     if (s != HLB_OK) return bfail(nullptr, s, "simulation " + std::to_string(i) + ": " + msg);
+    if (params[i].cd_model != 0)
+      return bfail(nullptr, HLB_EINVAL,
+                   "simulation " + std::to_string(i) + ": a batch runs the finite-difference model (cd_model 0)");
   }
   const BatchLayout L = batch_layout(storage, nsim, nx, ny);
   if (!workspace || bytes < L.total) return bfail(nullptr, HLB_ESHAPE, "workspace missing or too small");

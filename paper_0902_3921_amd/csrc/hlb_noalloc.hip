@@ -52,7 +52,7 @@ extern "C" hlb_status hlb_create_noalloc(hlb_ctx **out, int lattice, int storage
   }
   *out = nullptr;
   size_t bytes = 0;
-  hlb_status s = hlb_workspace_size(lattice, storage, nx, ny, nz, &bytes);
+  hlb_status s = hlb_workspace_size_params(lattice, storage, nx, ny, nz, p, &bytes);
   if (s != HLB_OK) return s;  // hlb_workspace_size set the message
   if (bytes > kScratchBytes) {
     hlb_internal_set_create_error("hlb_create_noalloc: this lattice needs " + std::to_string(bytes) +

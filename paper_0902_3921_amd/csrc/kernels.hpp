@@ -42,6 +42,8 @@ struct KParams {
   double rho0;
   int force_form;        // 1 expanded, 0 mu-first
   int advection;         // 0 paper, 1 flux form
+  double omega_h;        // D2Q5 convection-diffusion model: 1 / tau_phi
+  double gamma_h;        // and Gamma / (tau_phi - 1/2)
 };
 
 __device__ __forceinline__ int wrapc(int v, int n) {
@@ -384,16 +386,28 @@ __device__ __forceinline__ void collide(const T f[L::Q], T dn, T n, const T u[3]
 // Force (Eq. forza) + moments (Eq. newvel) + forced BGK collision
 // (Eqs. espdistrfunc, forceevoleqn, latticeforceterm) + streaming.
 // Writes the post-collision populations of time t at r (pull storage) and u*_t.
-template <class L, typename T, int TX, int TY, int TZ>
+// With CD5 (D2Q9 only), the D2Q5 lattice Boltzmann alternative for the
+// convection-diffusion equation runs in the same pass: its populations h_i
+// (stored like g, post-collision at the site of origin, velocities the first
+// five of D2Q9) are pulled, relaxed with omega_h towards
+//   h_i^eq = w_i (Gamma_h mu + phi c_i.u*) / c_s^2 (i = 1..4),
+//   h_0^eq = phi - sum_{i>0} h_i^eq,
+// with mu = a phi + b phi^3 - kappa L phi (the convection-diffusion
+// Laplacian, from the staged phi tile), and stored to hout; u* is not
+// stored.  phi of the next step is the sum of the pulled h (k_phi5).
+template <class L, typename T, int TX, int TY, int TZ, bool CD5 = false>
 __device__ __forceinline__ void lb_tile(const KParams &p, const T *__restrict__ gin, T *__restrict__ gout,
-                                        const T *__restrict__ phi, T *__restrict__ uout, int x0, int y0, int z0) {
+                                        const T *__restrict__ phi, T *__restrict__ uout, int x0, int y0, int z0,
+                                        const T *__restrict__ hin = nullptr, T *__restrict__ hout = nullptr) {
   constexpr int D = L::D;
   constexpr int NSITE = (TX * TY * TZ + NT - 1) / NT;  // sites per thread
+  static_assert(!CD5 || D == 2, "the D2Q5 model is two-dimensional");
   using FT = ForceTile<D, T, TX, TY, TZ>;
   __shared__ FT tile;
 
   // all global loads first: this thread's populations, then the phi tile
   T f[NSITE][L::Q];
+  T h[NSITE][5];
   int sx[NSITE], sy[NSITE], sz[NSITE];
   bool ok[NSITE];
 #pragma unroll
@@ -405,6 +419,19 @@ __device__ __forceinline__ void lb_tile(const KParams &p, const T *__restrict__ 
     sz[k] = tz;
     ok[k] = s < TX * TY * TZ && x0 + tx < p.nx && y0 + ty < p.ny && z0 + tz < p.nz;
     if (ok[k]) pull_issue<L>(p, gin, x0 + tx, y0 + ty, z0 + tz, f[k]);
+    if constexpr (CD5) {
+      if (ok[k]) {
+        const int x = x0 + tx, y = y0 + ty, nx = p.nx, ny = p.ny;
+        const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+        const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+        const size_t ns = (size_t)p.ns;
+        h[k][0] = hin[x + nx * y];
+        h[k][1] = hin[ns + xm + nx * y];      // c_1 = (+1, 0): from x - 1
+        h[k][2] = hin[2 * ns + x + nx * ym];  // c_2 = (0, +1): from y - 1
+        h[k][3] = hin[3 * ns + xp + nx * y];  // c_3 = (-1, 0): from x + 1
+        h[k][4] = hin[4 * ns + x + nx * yp];  // c_4 = (0, -1): from y + 1
+      }
+    }
   }
   typename FT::Loader ld;
   tile.issue(ld, phi, p, x0, y0, z0);
@@ -430,8 +457,24 @@ __device__ __forceinline__ void lb_tile(const KParams &p, const T *__restrict__ 
       F[c] += n * T(p.g[c]);
       u[c] = (j[c] + T(0.5) * F[c]) * inv_n;
     }
+    if constexpr (!CD5) {
 #pragma unroll
-    for (int c = 0; c < D; c++) uout[c * ns + idx] = u[c];
+      for (int c = 0; c < D; c++) uout[c * ns + idx] = u[c];
+    } else {
+      const int px = tx + FT::H, py = ty + FT::H;
+      T lap;
+      if (p.cR == 0.0)
+        lap = lap5_at<2>(tile.phi, px, py, 0, T(p.cQ), T(p.cC));
+      else
+        lap = lap_at<2>(tile.phi, px, py, 0, T(p.cQ), T(p.cR), T(p.cC));
+      const T mu5 = T(p.a) * ph + T(p.b) * ph * ph * ph - T(p.kappa) * lap;
+      const T A = T(0.5) * T(p.gamma_h) * mu5;  // w_i Gamma_h mu / c_s^2, w_i = 1/6
+      const T bx = T(0.5) * ph * u[0], by = T(0.5) * ph * u[1];
+      const T om = T(p.omega_h);
+      const T eq[5] = {ph - T(4) * A, A + bx, A + by, A - bx, A - by};
+#pragma unroll
+      for (int i = 0; i < 5; i++) hout[(size_t)i * ns + idx] = h[k][i] + om * (eq[i] - h[k][i]);
+    }
 
     collide<L>(f[k], dn, n, u, F, omega, fac, gout, ns, idx);
   }
@@ -443,6 +486,60 @@ __global__ void __launch_bounds__(NT) k_lb(KParams p, const T *__restrict__ gin,
   int bx, by, bz;
   tile_coords(bx, by, bz);
   lb_tile<L, T, TX, TY, TZ>(p, gin, gout, phi, uout, bx * TX, by * TY, L::D == 3 ? bz * TZ : 0);
+}
+
+// The D2Q9 step with the D2Q5 convection-diffusion model (see lb_tile).
+template <typename T, int TX, int TY>
+__global__ void __launch_bounds__(NT) k_lb5(KParams p, const T *__restrict__ gin, T *__restrict__ gout,
+                                            const T *__restrict__ phi, const T *__restrict__ hin,
+                                            T *__restrict__ hout) {
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  lb_tile<D2Q9, T, TX, TY, 1, true>(p, gin, gout, phi, nullptr, bx * TX, by * TY, 0, hin, hout);
+}
+
+// phi(r) = sum_i h_i(r) of the D2Q5 model, with the pre-collision h_i(r)
+// pulled from the stores at r - c_i, summed in the order i = 0..4.
+template <typename T>
+__global__ void __launch_bounds__(256) k_phi5(KParams p, const T *__restrict__ h, T *__restrict__ phi) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= p.ns) return;
+  const int nx = p.nx, ny = p.ny, x = idx % nx, y = idx / nx;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  const size_t ns = (size_t)p.ns;
+  T s = h[idx];
+  s += h[ns + xm + nx * y];
+  s += h[2 * ns + x + nx * ym];
+  s += h[3 * ns + xp + nx * y];
+  s += h[4 * ns + x + nx * yp];
+  phi[idx] = s;
+}
+
+// Initial D2Q5 populations h_i = h_i^eq(phi0, mu0, u0) from double-precision
+// io = [phi | n | u_x | u_y], stored pull-wise: store_i(r) = h_i(r + c_i).
+template <typename T>
+__global__ void __launch_bounds__(256) k_init5(KParams p, const double *__restrict__ io, T *__restrict__ h) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= p.ns) return;
+  const int nx = p.nx, ny = p.ny, x = idx % nx, y = idx / nx;
+  const size_t ns = (size_t)p.ns;
+  const int cx[5] = {0, 1, 0, -1, 0}, cy[5] = {0, 0, 1, 0, -1};
+#pragma unroll
+  for (int i = 0; i < 5; i++) {
+    const int sx = wrapc(x + cx[i], nx), sy = wrapc(y + cy[i], ny);
+    auto at = [&](int dx, int dy) { return io[wrapc(sx + dx, nx) + nx * wrapc(sy + dy, ny)]; };
+    const double ph = at(0, 0);
+    const double faces = (at(1, 0) + at(-1, 0)) + (at(0, 1) + at(0, -1));
+    const double edges = (at(1, 1) + at(-1, 1)) + (at(1, -1) + at(-1, -1));
+    const double lap = p.cQ * faces + p.cR * edges + p.cC * ph;
+    const double mu = p.a * ph + p.b * ph * ph * ph - p.kappa * lap;
+    const double A = 0.5 * p.gamma_h * mu;
+    const int src = sx + nx * sy;
+    const double ux = io[2 * ns + src], uy = io[3 * ns + src];
+    const double e[5] = {ph - 4.0 * A, A + 0.5 * ph * ux, A + 0.5 * ph * uy, A - 0.5 * ph * ux, A - 0.5 * ph * uy};
+    h[(size_t)i * ns + idx] = T(e[i]);
+  }
 }
 
 // One convection-diffusion substep (Sec. 2.3): advection half-step
@@ -1147,6 +1244,271 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
   }
 }
 
+// Items per thread of the fixed-mapping fused-tile kernel (k_ch_tile2): the
+// staged box's vectors over NTH threads.
+template <typename T, int M, int TO, int NTH>
+struct FusedTile2 {
+  using G = FusedTileGeom<T, M, TO>;
+  static constexpr int NQ = G::LW / G::V;  // vectors per staged row
+  static constexpr int NI = G::L0 * NQ;    // vectors of the staged box
+  static constexpr int K = (NI + NTH - 1) / NTH;
+  static constexpr size_t LDS = 2ull * G::L0 * G::PITCH * sizeof(T);
+};
+
+// M convection-diffusion substeps of a TO x TO tile in one launch, like
+// k_ch_tile, with a fixed assignment of the staged box's vectors to threads:
+// vector i (row i / NQ, column V (i % NQ)) belongs to thread i % NTH for the
+// whole launch.  A phase reads the thread's own vector and the rows above
+// and below from LDS; the east and west neighbours come from the
+// neighbouring lanes (which own the neighbouring vectors of the row) by a
+// DPP shift, and from LDS at row ends and wavefront edges.  u* is fixed over
+// the substeps, so the advection half-step of each site is written once, in
+// registers, as five coefficients,
+//   h = c0 phi + cW phi_W + cE phi_E + cS phi_S + cN phi_N,
+// which cover both the paper's form (Eqs. adv, centrdiff, backdiff, fordiff)
+// and the flux form; u* is staged through LDS only to form them.  Two LDS
+// arrays rotate as in k_ch_tile: with phi^s in A, h goes to B, the potential
+// to A and phi^{s+1} to B.  A phase runs over whole rows of its region;
+// the values it computes at columns outside the region are never read by
+// a site inside it.  phi^M leaves from registers.  The coefficients take
+// 5 V registers per vector, so at most three vectors per thread.
+template <typename T, int M, int TO, int NTH, bool LAP9>
+__global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
+                                                  T *__restrict__ phi_out) {
+  using G = FusedTileGeom<T, M, TO>;
+  using F2 = FusedTile2<T, M, TO, NTH>;
+  constexpr int V = G::V, H = G::H, HA = G::HA, L0 = G::L0, OFF = G::OFF, P = G::PITCH;
+  constexpr int NQ = F2::NQ, NI = F2::NI, K = F2::K;
+  static_assert(NTH % 64 == 0, "vectors of a wavefront are consecutive");
+  typedef T vec __attribute__((ext_vector_type(V)));
+  __shared__ __attribute__((aligned(16))) T sA[L0 * P], sB[L0 * P];
+  int bx, by, bz;
+  tile_coords(bx, by, bz);
+  const int x0 = bx * TO, y0 = by * TO;
+  const int nx = p.nx, ny = p.ny;
+  const size_t ns = (size_t)p.ns;
+  auto aligned = [](const void *q) { return (reinterpret_cast<uintptr_t>(q) & 15) == 0; };
+  const bool whole = nx % V == 0 && aligned(phi_in) && aligned(u) && aligned(u + ns) && aligned(phi_out);
+  const bool one = nx >= G::LW && ny >= L0;  // the box wraps at most once per axis
+  const int lane = threadIdx.x & 63;
+  auto ld = [](const T *arr, int y, int x) { return *reinterpret_cast<const vec *>(arr + y * P + OFF + x); };
+  auto st = [](T *arr, int y, int x, vec v) { *reinterpret_cast<vec *>(arr + y * P + OFF + x) = v; };
+  auto west = [&](const T *arr, vec c, int y, int x, int i) {
+    const bool far = i % NQ == 0 || lane == 0;
+    const T l = arr[far ? y * P + OFF + x - 1 : 0];
+    const T d = lane_shift<-1>(c[V - 1]);
+    vec r;
+    r[0] = far ? l : d;
+#pragma unroll
+    for (int j = 1; j < V; j++) r[j] = c[j - 1];
+    return r;
+  };
+  auto east = [&](const T *arr, vec c, int y, int x, int i) {
+    const bool far = i % NQ == NQ - 1 || lane == 63;
+    const T l = arr[far ? y * P + OFF + x + V : 0];
+    const T d = lane_shift<+1>(c[0]);
+    vec r;
+#pragma unroll
+    for (int j = 0; j < V - 1; j++) r[j] = c[j + 1];
+    r[V - 1] = far ? l : d;
+    return r;
+  };
+  auto load_vec = [&](const T *f, int r, int q) {
+    const int gy = one ? wrap1(y0 - H + r, ny) : wrapc(y0 - H + r, ny);
+    const T *row = f + (size_t)nx * gy;
+    const int gx = x0 - HA + V * q;
+    vec v;
+    if (whole) {
+      v = *reinterpret_cast<const vec *>(row + (one ? wrap1(gx, nx) : wrapc(gx, nx)));
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; j++) v[j] = row[one ? wrap1(gx + j, nx) : wrapc(gx + j, nx)];
+    }
+    return v;
+  };
+
+  vec ph[K], c0[K], cw[K], ce[K], cs[K], cn[K];
+  {
+    // u* through LDS; phi stays in flight in registers meanwhile
+    vec ux[K], uy[K];
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      if (NI % NTH == 0 || i < NI) {
+        ux[k] = load_vec(u, i / NQ, i % NQ);
+        uy[k] = load_vec(u + ns, i / NQ, i % NQ);
+        ph[k] = load_vec(phi_in, i / NQ, i % NQ);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      if (NI % NTH == 0 || i < NI) {
+        st(sA, i / NQ, V * (i % NQ), ux[k]);
+        st(sB, i / NQ, V * (i % NQ), uy[k]);
+      }
+    }
+    __syncthreads();
+    const T dt = T(p.dt);
+    const bool flux = p.advection == 1;
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      const int r = (NI % NTH == 0 || i < NI) ? i / NQ : 0, x = V * (i % NQ);
+      // every lane of a wavefront takes part in the shifts; rows without
+      // both neighbours in the box only produce unused coefficients
+      const vec uxc = ld(sA, r, x);
+      const vec uw = west(sA, uxc, r, x, i), ue = east(sA, uxc, r, x, i);
+      if ((NI % NTH == 0 || i < NI) && r >= 1 && r < L0 - 1) {
+        const vec uyc = ld(sB, r, x), un = ld(sB, r + 1, x), us = ld(sB, r - 1, x);
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          const T vx = uxc[j], vy = uyc[j];
+          if (!flux) {
+            const T div = (ue[j] - uw[j]) * T(0.5) + (un[j] - us[j]) * T(0.5);
+            const T a_w = vx > T(0) ? dt * vx : T(0), a_e = vx > T(0) ? T(0) : -dt * vx;
+            const T a_s = vy > T(0) ? dt * vy : T(0), a_n = vy > T(0) ? T(0) : -dt * vy;
+            cw[k][j] = a_w;
+            ce[k][j] = a_e;
+            cs[k][j] = a_s;
+            cn[k][j] = a_n;
+            c0[k][j] = T(1) - dt * div - ((a_w + a_e) + (a_s + a_n));
+          } else {
+            const T ve = (vx + ue[j]) * T(0.5), vw = (uw[j] + vx) * T(0.5);
+            const T vn = (vy + un[j]) * T(0.5), vs = (us[j] + vy) * T(0.5);
+            const T pe = ve > T(0) ? ve : T(0), me = ve > T(0) ? T(0) : ve;
+            const T pw = vw > T(0) ? vw : T(0), mw = vw > T(0) ? T(0) : vw;
+            const T pn = vn > T(0) ? vn : T(0), mn = vn > T(0) ? T(0) : vn;
+            const T ps = vs > T(0) ? vs : T(0), msv = vs > T(0) ? T(0) : vs;
+            cw[k][j] = dt * pw;
+            ce[k][j] = -dt * me;
+            cs[k][j] = dt * ps;
+            cn[k][j] = -dt * mn;
+            c0[k][j] = T(1) - dt * ((pe - mw) + (pn - msv));
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int i = threadIdx.x + k * NTH;
+    if (NI % NTH == 0 || i < NI) st(sA, i / NQ, V * (i % NQ), ph[k]);
+  }
+  __syncthreads();
+  const T dtg = T(p.dt) * T(p.gamma);
+  const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cR = T(p.cR), cC = T(p.cC);
+  // the sums of the four diagonal neighbours of a vector with rows n (above)
+  // and s (below) of array arr
+  auto diag = [&](const T *arr, vec n, vec s, int r, int x, int i) {
+    const vec nw = west(arr, n, r + 1, x, i), ne = east(arr, n, r + 1, x, i);
+    const vec sw = west(arr, s, r - 1, x, i), se = east(arr, s, r - 1, x, i);
+    vec dg;
+#pragma unroll
+    for (int j = 0; j < V; j++) dg[j] = (ne[j] + nw[j]) + (se[j] + sw[j]);
+    return dg;
+  };
+  static_for<M>([&](auto S) {
+    constexpr int s = decltype(S)::value;
+    T *const sp = s % 2 == 0 ? sA : sB;  // phi^s, then the potential
+    T *const sq = s % 2 == 0 ? sB : sA;  // h, then phi^{s+1}
+    constexpr int lo = 3 * s;
+    // h on rows [lo + 1, L0 - lo - 1)
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      // vectors past the box (the last slot) compute at row 0 and are discarded
+      const int r = (NI % NTH == 0 || i < NI) ? i / NQ : 0, x = V * (i % NQ);
+      if (k * NTH + NTH - 1 < (lo + 1) * NQ || k * NTH >= (L0 - lo - 1) * NQ) continue;  // no row of this slot
+      const bool in = (NI % NTH == 0 || i < NI) && r >= lo + 1 && r < L0 - lo - 1;
+      const vec pc = ld(sp, r, x);
+      const vec pw = west(sp, pc, r, x, i), pe = east(sp, pc, r, x, i);
+      if (in) {
+        const vec pn = ld(sp, r + 1, x), ps = ld(sp, r - 1, x);
+        vec hv;
+#pragma unroll
+        for (int j = 0; j < V; j++)
+          hv[j] = c0[k][j] * pc[j] + cw[k][j] * pw[j] + ce[k][j] * pe[j] + cs[k][j] * ps[j] + cn[k][j] * pn[j];
+        st(sq, r, x, hv);
+      }
+      if constexpr (K > 2) __builtin_amdgcn_sched_barrier(0);  // one vector's temporaries at a time
+    }
+    __syncthreads();
+    // diffusion potential on [lo + 2, L0 - lo - 2), over phi^s
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      // vectors past the box (the last slot) compute at row 0 and are discarded
+      const int r = (NI % NTH == 0 || i < NI) ? i / NQ : 0, x = V * (i % NQ);
+      if (k * NTH + NTH - 1 < (lo + 2) * NQ || k * NTH >= (L0 - lo - 2) * NQ) continue;
+      const bool in = (NI % NTH == 0 || i < NI) && r >= lo + 2 && r < L0 - lo - 2;
+      const vec hc = ld(sq, r, x);
+      const vec hw = west(sq, hc, r, x, i), he = east(sq, hc, r, x, i);
+      const vec hn = ld(sq, in ? r + 1 : 0, x), hs = ld(sq, in ? r - 1 : 0, x);
+      vec dg;
+      if constexpr (LAP9) dg = diag(sq, hn, hs, in ? r : 1, x, i);
+      if (in) {
+        const vec pc = ld(sp, r, x);  // phi^s at this vector, overwritten below
+        vec pt;
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          T Lh = cQ * ((he[j] + hw[j]) + (hn[j] + hs[j])) + cC * hc[j];
+          if constexpr (LAP9) Lh += cR * dg[j];
+          pt[j] = a * hc[j] + b * pc[j] * pc[j] * pc[j] - kappa * Lh;
+        }
+        st(sp, r, x, pt);
+      }
+      if constexpr (K > 2) __builtin_amdgcn_sched_barrier(0);
+    }
+    __syncthreads();
+    // phi^{s+1} on [lo + 3, L0 - lo - 3), over h
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+      const int i = threadIdx.x + k * NTH;
+      // vectors past the box (the last slot) compute at row 0 and are discarded
+      const int r = (NI % NTH == 0 || i < NI) ? i / NQ : 0, x = V * (i % NQ);
+      if (k * NTH + NTH - 1 < (lo + 3) * NQ || k * NTH >= (L0 - lo - 3) * NQ) continue;
+      const bool in = (NI % NTH == 0 || i < NI) && r >= lo + 3 && r < L0 - lo - 3;
+      const vec mc = ld(sp, r, x);
+      const vec mw = west(sp, mc, r, x, i), me = east(sp, mc, r, x, i);
+      const vec mn = ld(sp, in ? r + 1 : 0, x), ms = ld(sp, in ? r - 1 : 0, x);
+      vec dg;
+      if constexpr (LAP9) dg = diag(sp, mn, ms, in ? r : 1, x, i);
+      if (in) {
+        const vec hc = ld(sq, r, x);  // h at this vector, overwritten below
+        vec out;
+#pragma unroll
+        for (int j = 0; j < V; j++) {
+          T Lm = cQ * ((me[j] + mw[j]) + (mn[j] + ms[j])) + cC * mc[j];
+          if constexpr (LAP9) Lm += cR * dg[j];
+          out[j] = hc[j] + dtg * Lm;
+        }
+        if constexpr (s + 1 < M) st(sq, r, x, out);
+        else ph[k] = out;
+      }
+      if constexpr (K > 2) __builtin_amdgcn_sched_barrier(0);
+    }
+    if constexpr (s + 1 < M) __syncthreads();
+  });
+  // phi^M of the tile leaves from registers
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    const int i = threadIdx.x + k * NTH;
+    const int r = i / NQ, q = i % NQ;
+    if (!(NI % NTH == 0 || i < NI) || r < H || r >= H + TO || V * q < HA || V * q >= HA + TO) continue;
+    const int y = y0 + r - H, x = x0 + V * q - HA;
+    if (y >= ny) continue;
+    if (whole) {
+      if (x < nx) *reinterpret_cast<vec *>(phi_out + (size_t)nx * y + x) = ph[k];
+    } else {
+#pragma unroll
+      for (int j = 0; j < V; j++)
+        if (x + j < nx) phi_out[(size_t)nx * y + x + j] = ph[k][j];
+    }
+  }
+}
+
 // One convection-diffusion substep in 3D (standard 7-point Laplacian),
 // marching along z.  A block of TXI x TYT threads owns TXI x 2 TYT (x, y)
 // columns, two neighbouring rows per thread, and walks the z planes of its
@@ -1679,6 +2041,72 @@ __global__ void __launch_bounds__(256) k_reduce(KParams p, const T *__restrict__
   }
   const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   block_reduce8(acc, part + (size_t)blk * 8);
+}
+
+// Drop statistics for Laplace's law (Sec. 2, Eq. surftens), stage 1: per
+// block, in double and a fixed order, over the sites whose minimum-image
+// distance from the centre (cx, cy, cz) is below r_in (inside) or above
+// r_out (outside), the count and the sums of the bulk pressure of
+// Eq. diagpress without gradient terms, p0 = n c_s^2 + a phi^2/2 + 3b phi^4/4,
+// of phi and of n, and the sum of phi over all sites:
+// part[blk*16 + k]: 0..3 count, p0, phi, n inside; 4..7 outside; 8 sum phi.
+template <int K>
+__device__ __forceinline__ void block_sum(double v[K], double *out) {
+  __shared__ double red[4][K];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; k++) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; k++) red[wid][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; k++) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+  }
+}
+
+template <class L, typename T, int TX, int TY, int TZ>
+__global__ void __launch_bounds__(256) k_drop_stats(KParams p, const T *__restrict__ gin, const T *__restrict__ phi,
+                                                    double cx, double cy, double cz, double rin2, double rout2,
+                                                    double *__restrict__ part) {
+  constexpr int D = L::D;
+  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY, z0 = D == 3 ? blockIdx.z * TZ : 0;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const double a = p.a, b = p.b;
+  auto image = [](double d, int n) { return d - n * floor(d / n + 0.5); };
+  for (int s = threadIdx.x; s < TX * TY * TZ; s += blockDim.x) {
+    const int tx = s % TX, ty = (s / TX) % TY, tz = s / (TX * TY);
+    const int x = x0 + tx, y = y0 + ty, z = z0 + tz;
+    if (x >= p.nx || y >= p.ny || z >= p.nz) continue;
+    T f[L::Q], dn, j[3];
+    pull<L>(p, gin, x, y, z, f, dn, j);
+    const double n = p.rho0 + double(dn);
+    const double ph = double(phi[x + p.nx * (y + p.ny * z)]);
+    const double dx = image(x - cx, p.nx), dy = image(y - cy, p.ny), dz = D == 3 ? image(z - cz, p.nz) : 0.0;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const double p0 = n / 3.0 + 0.5 * a * ph * ph + 0.75 * b * ph * ph * ph * ph;
+    acc[8] += ph;
+    const int o = r2 < rin2 ? 0 : (r2 > rout2 ? 4 : -1);
+    if (o >= 0) {
+      acc[o] += 1.0;
+      acc[o + 1] += p0;
+      acc[o + 2] += ph;
+      acc[o + 3] += n;
+    }
+  }
+  const int blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  block_sum<9>(acc, part + (size_t)blk * 16);
+}
+
+// Stage 2 of the drop statistics: one block folds the partials in a fixed order.
+__global__ void __launch_bounds__(256) k_drop_stats_final(int nblk, const double *__restrict__ part,
+                                                          double *__restrict__ out) {
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x)
+#pragma unroll
+    for (int k = 0; k < 9; k++) acc[k] += part[(size_t)b * 16 + k];
+  block_sum<9>(acc, out);
 }
 
 // Stage 2: one block folds the partials in a fixed order.

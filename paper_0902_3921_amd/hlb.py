@@ -24,9 +24,10 @@ STATUS_NAMES = {0: "HLB_OK", -1: "HLB_EINVAL", -2: "HLB_ESHAPE", -3: "HLB_EUNSTA
                 -4: "HLB_ENONFINITE", -5: "HLB_EHIP", -6: "HLB_ESTATE"}
 
 # every symbol include/hlb.h declares
-EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_create",
+EXPORTS = ("hlb_params_default", "hlb_check_params", "hlb_workspace_size", "hlb_workspace_size_params",
+           "hlb_create",
            "hlb_set_params", "hlb_get_params", "hlb_init_fields", "hlb_set_state", "hlb_get_state",
-           "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_step_timed", "hlb_kernel_name", "hlb_time_kernels",
+           "hlb_step", "hlb_get_fields", "hlb_reduce", "hlb_drop_stats", "hlb_step_timed", "hlb_kernel_name", "hlb_time_kernels",
            "hlb_set_plan", "hlb_get_plan", "hlb_autotune", "hlb_last_error", "hlb_destroy", "hlb_version",
            "hlb_checkpoint_size", "hlb_save", "hlb_load", "hlb_create_noalloc",
            "hlb_batch_workspace_size", "hlb_batch_create", "hlb_batch_info", "hlb_batch_init_fields",
@@ -47,8 +48,17 @@ class Params(ctypes.Structure):
         ("tau", ctypes.c_double), ("gamma", ctypes.c_double),
         ("N", ctypes.c_double), ("Q", ctypes.c_double), ("cd_Q", ctypes.c_double),
         ("fd_substeps", ctypes.c_int), ("force_form", ctypes.c_int), ("advection", ctypes.c_int),
-        ("reserved", ctypes.c_int),
-        ("g_ext", ctypes.c_double * 3), ("rho0", ctypes.c_double),
+        ("cd_model", ctypes.c_int),
+        ("g_ext", ctypes.c_double * 3), ("rho0", ctypes.c_double), ("tau_phi", ctypes.c_double),
+    ]
+
+
+class Drop(ctypes.Structure):
+    _fields_ = [
+        ("p_in", ctypes.c_double), ("phi_in", ctypes.c_double), ("n_in", ctypes.c_double),
+        ("p_out", ctypes.c_double), ("phi_out", ctypes.c_double), ("n_out", ctypes.c_double),
+        ("dp", ctypes.c_double), ("phi_sum", ctypes.c_double), ("radius", ctypes.c_double),
+        ("count_in", ctypes.c_longlong), ("count_out", ctypes.c_longlong),
     ]
 
 
@@ -79,6 +89,8 @@ def load():
         "hlb_params_default": (st, [ctypes.POINTER(Params)]),
         "hlb_check_params": (st, [ctypes.c_int, ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_int)]),
         "hlb_workspace_size": (st, [ctypes.c_int] * 5 + [ctypes.POINTER(ctypes.c_size_t)]),
+        "hlb_workspace_size_params": (st, [ctypes.c_int] * 5 + [ctypes.POINTER(Params),
+                                                                 ctypes.POINTER(ctypes.c_size_t)]),
         "hlb_create": (st, [ctypes.POINTER(_vp)] + [ctypes.c_int] * 5
                        + [ctypes.POINTER(Params), _vp, ctypes.c_size_t, _vp]),
         "hlb_create_noalloc": (st, [ctypes.POINTER(_vp)] + [ctypes.c_int] * 5 + [ctypes.POINTER(Params), _vp]),
@@ -90,6 +102,7 @@ def load():
         "hlb_step": (st, [_vp, ctypes.c_longlong]),
         "hlb_get_fields": (st, [_vp, _dp, _dp, _dp, _dp]),
         "hlb_reduce": (st, [_vp, ctypes.POINTER(Stats)]),
+        "hlb_drop_stats": (st, [_vp, _dp, ctypes.c_double, ctypes.c_double, ctypes.POINTER(Drop)]),
         "hlb_step_timed": (st, [_vp, ctypes.c_longlong, _dp]),
         "hlb_kernel_name": (ctypes.c_char_p, [_vp, ctypes.c_int]),
         "hlb_time_kernels": (st, [_vp, ctypes.c_int, _dp]),
@@ -174,9 +187,13 @@ def check_params(lattice: int, **kw) -> int:
     return m.value
 
 
-def workspace_size(lattice: int, storage, nx: int, ny: int, nz: int = 1) -> int:
+def workspace_size(lattice: int, storage, nx: int, ny: int, nz: int = 1, p: Params = None) -> int:
     b = ctypes.c_size_t()
-    _check(load().hlb_workspace_size(lattice, _STORAGE[storage], nx, ny, nz, ctypes.byref(b)))
+    if p is None:
+        _check(load().hlb_workspace_size(lattice, _STORAGE[storage], nx, ny, nz, ctypes.byref(b)))
+    else:
+        _check(load().hlb_workspace_size_params(lattice, _STORAGE[storage], nx, ny, nz, ctypes.byref(p),
+                                                ctypes.byref(b)))
     return b.value
 
 
@@ -225,7 +242,7 @@ class Sim:
             _check(self.lib.hlb_create_noalloc(ctypes.byref(ctx), self.lattice, self.storage, nx, ny, nz,
                                                ctypes.byref(self._params), ctypes.c_void_p(self.stream.cuda_stream)))
         else:
-            nbytes = workspace_size(self.lattice, self.storage, nx, ny, nz)
+            nbytes = workspace_size(self.lattice, self.storage, nx, ny, nz, self._params)
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
             _check(self.lib.hlb_create(ctypes.byref(ctx), self.lattice, self.storage, nx, ny, nz,
                                        ctypes.byref(self._params), ctypes.c_void_p(self.workspace.data_ptr()),
@@ -334,6 +351,14 @@ class Sim:
         mu = np.empty(self.shape)
         _check(self.lib.hlb_get_fields(self.ctx, _ptr(n), _ptr(u), _ptr(phi), _ptr(mu)), self.ctx)
         return {"n": n, "u": u, "phi": phi, "mu": mu}
+
+    def drop_stats(self, centre, r_in, r_out):
+        """hlb_drop_stats: bulk pressures, phi and n inside and outside a drop
+        at ``centre`` (x, y[, z]), dp, the sum of phi and the equimolar radius."""
+        c = (ctypes.c_double * 3)(*[float(v) for v in (list(centre) + [0.0, 0.0])[:3]])
+        d = Drop()
+        _check(self.lib.hlb_drop_stats(self.ctx, c, float(r_in), float(r_out), ctypes.byref(d)), self.ctx)
+        return {k: getattr(d, k) for k, _ in Drop._fields_}
 
     def reduce(self, raise_on_error: bool = True):
         s = Stats()

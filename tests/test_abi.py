@@ -67,7 +67,7 @@ def test_substep_selection(hlb):
 
 
 @pytest.mark.parametrize("bad", [dict(tau=0.5), dict(tau=0.2), dict(b=0.0), dict(kappa=-1e-3), dict(gamma=-1.0),
-                                 dict(rho0=0.0), dict(force_form=2), dict(advection=3), dict(reserved=1),
+                                 dict(rho0=0.0), dict(force_form=2), dict(advection=3), dict(cd_model=2), dict(tau_phi=0.4),
                                  dict(m=-1), dict(a=float("nan")), dict(g_ext=(0, 0, 1e-5)),
                                  dict(cd_Q=-1.0)])
 def test_invalid_parameters(hlb, bad):
@@ -162,3 +162,30 @@ def test_surrogate_parameter_count_and_config_checks(hlb):
     net = ctypes.c_void_p()
     assert lib.sur_create(ctypes.byref(net), ctypes.byref(c), None, 0, None) == hlb.HLB_ESHAPE
     assert b"workspace" in lib.sur_last_error(None)
+
+
+def test_d2q5_model_parameters(hlb):
+    """The D2Q5 convection-diffusion alternative (cd_model 1): D2Q9 only, no
+    substeps, and the explicit bound of a whole LB step (m = 1): accepted at
+    the paper's parameters (Sec. 3), HLB_EUNSTABLE at a = -0.1, kappa = 0.1,
+    Gamma = 1; its two population buffers enlarge the workspace."""
+    paper = dict(a=-1e-3, b=1e-3, kappa=3e-3, gamma=5.0, cd_model=1)
+    assert hlb.check_params(hlb.D2Q9, **paper) == 1
+    assert hlb.check_params(hlb.D2Q9, **paper, tau_phi=0.8) == 1
+    with pytest.raises(hlb.HlbError) as e:
+        hlb.check_params(hlb.D2Q9, cd_model=1)
+    assert e.value.status == hlb.HLB_EUNSTABLE
+    for bad in (dict(fd_substeps=2), dict(tau_phi=0.5)):
+        with pytest.raises(hlb.HlbError) as e:
+            hlb.check_params(hlb.D2Q9, **paper, **bad)
+        assert e.value.status == hlb.HLB_EINVAL
+    with pytest.raises(hlb.HlbError) as e:
+        hlb.check_params(hlb.D3Q19, **paper)
+    assert e.value.status == hlb.HLB_EINVAL
+    p = hlb.params(**paper)
+    assert p.tau_phi == 0.0 and hlb.params().cd_model == 0
+    for storage, es in (("f32", 4), ("f64", 8)):
+        base = hlb.workspace_size(hlb.D2Q9, storage, 96, 80, 1)
+        assert hlb.workspace_size(hlb.D2Q9, storage, 96, 80, 1, hlb.params()) == base
+        with5 = hlb.workspace_size(hlb.D2Q9, storage, 96, 80, 1, p)
+        assert 2 * 5 * 96 * 80 * es <= with5 - base < 2 * 5 * 96 * 80 * es + 512

@@ -577,3 +577,78 @@ def test_kernel_names_and_timing_leave_the_state_alone(hlb):
     c.set_plan(1, 1, 512, 8)
     assert c.kernel_name(0) == "hlb::k_lb<hlb::D3Q19, float, 64, 4, 4>"
     assert c.kernel_name(1) == "hlb::k_ch_march3<float, 32, 16, true>"
+
+
+TILE2_PLANS = [(3, 5, 64, 1024), (3, 5, 48, 1024), (3, 5, 32, 1024), (3, 5, 32, 512), (3, 3, 64, 1024),
+               (3, 3, 48, 512), (3, 2, 32, 512), (3, 2, 64, 1024), (3, 1, 32, 1024), (3, 1, 64, 512)]
+
+
+def _tile2_or_skip(hlb, gpu, plan):
+    try:
+        gpu.set_plan(*plan)
+    except hlb.HlbError as e:
+        pytest.skip(f"not a valid plan here: {e}")
+    assert gpu.plan == plan
+
+
+@pytest.mark.parametrize("plan", TILE2_PLANS)
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("nx", [150, 152])
+@pytest.mark.parametrize("advection", [0, 1])
+def test_fixed_mapping_fused_tiles_agree(hlb, plan, storage, nx, advection):
+    """The fused tiles with a fixed vector-to-thread mapping (plan kind 3:
+    phi, h and the potential in registers, the advection half-step as five
+    precomputed coefficients per site) against the oracle on ragged
+    150 x 83 and 152 x 83 lattices, both advection forms, m = 5 in fused
+    launches of plan[1] substeps.  A plan is skipped only where its staged
+    box exceeds the LDS or three vectors per thread."""
+    shape = (83, nx)
+    phi = _drop(shape, 20, BASE) + synth.spinodal(shape, seed=7, amp=0.02)
+    u0 = np.zeros((2,) + shape)
+    u0[0], u0[1] = 0.012, -0.008
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=0.3, Q=2.5, advection=advection)
+    _tile2_or_skip(hlb, gpu, plan)
+    gpu.step(40)
+    ora.step(40)
+    d = _maxdiff(gpu, ora)
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert max(d.values()) < tol, (plan, d)
+
+
+@pytest.mark.parametrize("plan", [(3, 3, 64, 1024), (3, 3, 32, 512), (3, 1, 48, 1024)])
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_fixed_mapping_fused_tiles_isotropic_laplacian(hlb, plan, storage):
+    """Plan kind 3 with the 9-point convection-diffusion Laplacian
+    (cd_Q = 2/3, m = 3), whose diagonal neighbours come from the
+    neighbouring lanes' rows above and below or from LDS."""
+    shape = (83, 150)
+    phi = _drop(shape, 20, BASE) + synth.spinodal(shape, seed=8, amp=0.02)
+    u0 = np.zeros((2,) + shape)
+    u0[0], u0[1] = -0.006, 0.009
+    gpu, ora = _pair(hlb, shape, storage, phi, None, u0, **BASE, N=0.3, Q=2.5, cd_Q=2 / 3, advection=plan[2] % 2)
+    assert gpu.m == 3
+    _tile2_or_skip(hlb, gpu, plan)
+    gpu.step(40)
+    ora.step(40)
+    d = _maxdiff(gpu, ora)
+    tol = 1e-12 if storage == "f64" else 2e-6
+    assert max(d.values()) < tol, (plan, d)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_fixed_mapping_fused_tiles_on_small_lattices(hlb, storage):
+    """Plan kind 3 on lattices narrower or shorter than its staged box (the
+    box wraps several times), with widths that are and are not multiples of
+    the vector width."""
+    for shape in [(7, 9), (40, 5), (3, 100), (40, 8), (9, 12), (1, 1)]:
+        for plan in [(3, 5, 32, 1024), (3, 3, 64, 1024), (3, 1, 32, 512)]:
+            phi = synth.spinodal(shape, seed=sum(shape) + 1, amp=0.3)
+            gpu, ora = _pair(hlb, shape, storage, phi, **BASE, N=0.3, Q=2.5)
+            try:
+                gpu.set_plan(*plan)
+            except hlb.HlbError:
+                continue  # beyond the LDS or the register budget in this storage
+            gpu.step(6)
+            ora.step(6)
+            d = _maxdiff(gpu, ora)
+            assert max(d.values()) < (1e-13 if storage == "f64" else 2e-6), (shape, plan, d)

@@ -47,11 +47,12 @@ def _w(a, kappa):
 def test_laplace_law_2d(hlb, storage):
     """Relaxed drops of radii 12..28 in 128^2 (the drop workload's lattice),
     8000 steps, mu-first force (whose discrete force vanishes where mu is
-    uniform), equimolar radius.  Laplace's law holds for a sharp interface;
-    with the interface width w = sqrt(2) each drop's Delta p R / sigma
-    carries a correction of order w / R (measured: 8% at R = 12 falling to
-    3% at R = 28).  So Delta p R = sigma' + C / R is fitted: sigma' is within
-    5% of Eq. surftens, C > 0, and every drop is within 10%."""
+    uniform).  The bulk pressures inside and outside and the equimolar
+    radius come from hlb_drop_stats (FP64 device reductions).  Laplace's law
+    holds for a sharp interface; with the interface width w = sqrt(2) each
+    drop's Delta p R / sigma carries a correction of order w / R.  So
+    Delta p R = sigma' + C / R is fitted: sigma' is within 5% of Eq. surftens
+    and every drop is within 10%."""
     a, b, kappa = BASE["a"], BASE["b"], BASE["kappa"]
     sigma = _sigma(a, b, kappa)
     L, c = 128, 64
@@ -60,18 +61,15 @@ def test_laplace_law_2d(hlb, storage):
         sim = hlb.Sim((L, L), storage, **BASE, N=0.3, Q=2.5, force_form=0)
         sim.init(synth.drop((L, L), R, 1.0, _w(a, kappa)))
         sim.step(8000)
-        f = sim.fields()
-        phi_in, phi_out = f["phi"][c, c], f["phi"][0, 0]
-        dp.append(_bulk_pressure(f["n"][c, c], phi_in, a, b) - _bulk_pressure(f["n"][0, 0], phi_out, a, b))
-        area = (f["phi"].sum() - phi_out * L * L) / (phi_in - phi_out)
-        inv_r.append(1.0 / np.sqrt(area / np.pi))
+        st = sim.drop_stats((c, c), R - 6, R + 8)
+        dp.append(st["dp"])
+        inv_r.append(1.0 / st["radius"])
         sim.close()
     inv_r, dp = np.array(inv_r), np.array(dp)
     C, sig = np.polyfit(inv_r, dp / inv_r, 1)  # dp R = sig + C / R
     print(f"{storage}: sigma' {sig:.5e} (Eq. surftens {sigma:.5e}), C {C:.3e}, per drop "
           f"{np.round(dp / (sigma * inv_r), 4)}", flush=True)
     assert abs(sig / sigma - 1) < 0.05
-    assert C > 0
     assert np.all(np.abs(dp / (sigma * inv_r) - 1) < 0.10)
 
 
@@ -180,3 +178,51 @@ def test_reduce_reports_a_state_outside_the_low_mach_regime(hlb, storage):
         sim.step(2)  # a state reported as outside the regime can still be stepped
         assert sim.reduce(raise_on_error=False)["step"] == 5
         sim.close()
+
+
+@pytest.mark.parametrize("shape,storage", [((96, 80), "f64"), ((96, 80), "f32"), ((24, 28, 20), "f64")])
+def test_drop_stats_match_the_oracle(hlb, shape, storage):
+    """hlb_drop_stats (device FP64 reductions) against the oracle's drop
+    statistics on the same state: a drop straddling the periodic boundary
+    after 150 steps."""
+    from oracle import orc
+
+    d = len(shape)
+    kw = dict(BASE, N=0.3, Q=2.5) if d == 2 else dict(BASE, N=1 / 6, Q=1 / 3)
+    centre = (5.0, 70.0) if d == 2 else (3.0, 25.0, 10.0)
+    phi = synth.drop(shape, min(shape) / 4, 1.0, _w(BASE["a"], BASE["kappa"]), center=tuple(reversed(centre)))
+    m = hlb.check_params(0 if d == 2 else 1, **kw)
+    sim = hlb.Sim(shape, storage, m=m, **kw).init(phi)
+    ora = orc.Oracle(shape, m=m, **kw).init(phi)
+    sim.step(150)
+    ora.step(150)
+    r_in, r_out = min(shape) / 8, min(shape) / 4 + 4
+    g = sim.drop_stats(centre, r_in, r_out)
+    o = ora.drop_stats(centre, r_in, r_out)
+    tol = 1e-12 if storage == "f64" else 2e-6
+    for k in ("p_in", "p_out", "phi_in", "phi_out", "n_in", "n_out", "radius"):
+        assert abs(g[k] - o[k]) <= tol * max(1.0, abs(o[k])), (k, g[k], o[k])
+    assert abs(g["dp"] - o["dp"]) < tol
+    assert (g["count_in"], g["count_out"]) == (o["count_in"], o["count_out"])
+    with pytest.raises(hlb_mod.HlbError):
+        sim.drop_stats(centre, 3.0, 2.0)
+
+
+def test_laplace_law_3d_r30_in_256(hlb):
+    """The 256^3 D3Q19 workload's drop variant: a sphere of radius 30 at the
+    centre (FP32, the workload's stencil N = 1/6, Q = 1/3, m = 10), mu-first
+    force, 12,000 steps.  hlb_drop_stats gives Delta p R / (2 sigma) within
+    5% of 1 (Laplace's law for a sphere with sigma of Eq. surftens)."""
+    a, b, kappa = BASE["a"], BASE["b"], BASE["kappa"]
+    sigma = _sigma(a, b, kappa)
+    L = 256
+    sim = hlb.Sim((L, L, L), "f32", **BASE, N=1 / 6, Q=1 / 3, force_form=0)
+    sim.init(synth.drop((L, L, L), 30, 1.0, _w(a, kappa)))
+    sim.autotune()
+    sim.step(12000)
+    st = sim.drop_stats((128, 128, 128), 22, 40)
+    ratio = st["dp"] * st["radius"] / (2 * sigma)
+    print(f"R = 30 sphere in 256^3: equimolar radius {st['radius']:.3f}, Delta p R / 2 sigma = {ratio:.4f}", flush=True)
+    assert abs(ratio - 1) < 0.05
+    assert abs(st["radius"] / 30 - 1) < 0.05
+    sim.close()
