@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+N_CU, CLOCK_HZ = 256, 2.4e9  # MI355X compute units and peak engine clock
 # rocprofv3 counter scale, from a 1 GiB device copy (1 GiB read, 1 GiB written)
 # that reads FETCH_SIZE = 524,300 KiB and WRITE_SIZE = 1,048,576 KiB
 FETCH_SCALE, WRITE_SCALE = 2.0, 1.0
@@ -338,6 +339,7 @@ def run_surrogate(args):
     net = sur.Surrogate(batch=1)
     net.set_params(params)
     r = st.rollout(net, seed=100001, jumps=100, check_every=10, tol=1e-2, log=lambda *a, **k: None)
+    diag = surrogate_diagnostics(net, seed=100001, t0=st.T_FIRST)
     x = torch.from_numpy(np.zeros((1, st.SIZE, st.SIZE, 3), np.float32)).cuda()
     x[..., 0] = torch.rand((st.SIZE, st.SIZE), device="cuda") * 2 - 1
     y = torch.empty_like(x)
@@ -384,27 +386,63 @@ def run_surrogate(args):
                     "phi_rel_l2_at_checks": r["errors"],
                     "persistence_phi_rel_l2": r["persistence_errors"],
                     "forward_ms": ms_total, "conv_ms": ms_conv},
+        "error_per_jump": diag["error_per_jump"],
+        "solver_fp32_vs_fp64": diag["solver_fp32_vs_fp64"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
 
-def profile_figures(name, kernel_name):
+def surrogate_diagnostics(net, seed, t0, jumps=10):
+    """The surrogate's relative L2 phi error after 1..jumps jumps from the
+    FP32 solver's state at t0, and the FP32 solver's distance from the FP64
+    solver started from the same state after the same jumps (how
+    predictable the target is)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_0902_3921_amd import hlb, surrogate_train as st
+
+    S, J = st.SIZE, st.JUMP
+    ref = hlb.Sim((S, S), "f64", **st.PHYS).init(synth.spinodal((S, S), seed, 0.01))
+    ref.step(t0)
+    f, ph = ref.state()
+    s32 = hlb.Sim((S, S), "f32", **st.PHYS)
+    s32.set_state(f, ph)
+    x = torch.from_numpy(st.state_of(s32.fields())[None]).cuda().contiguous()
+    sur_err, fp32_err = [], []
+    for _ in range(jumps):
+        ref.step(J)
+        s32.step(J)
+        net.forward(x, x)
+        r64 = ref.fields()["phi"]
+        r32 = s32.fields()["phi"]
+        sur_err.append(float(np.linalg.norm(x[0, ..., 0].cpu().numpy() - r32) / np.linalg.norm(r32)))
+        fp32_err.append(float(np.linalg.norm(r32 - r64) / np.linalg.norm(r64)))
+    ref.close()
+    s32.close()
+    return {"error_per_jump": sur_err, "solver_fp32_vs_fp64": fp32_err}
+
+
+def profile_figures(name, kernel_name, want_valu=False):
     """From the committed rocprofv3 summary of this workload, for the kernel
     of exactly this name (the full template instantiation): HBM bytes per
     dispatch (FETCH_SIZE and WRITE_SIZE, KiB per dispatch, scaled by the copy
     calibration) and the kernel-trace average duration in us.  None for a
     figure the summary does not hold, and for both if the summary was taken
-    on different library sources."""
+    on different library sources.  With want_valu, also the kernel's
+    SQ_INSTS_VALU per dispatch (wavefront instructions), or None."""
     from paper_0902_3921_amd import build
 
     path = os.path.join(ROOT, "profiles", f"{name}.md")
+    none = (None, None, None) if want_valu else (None, None)
     if not os.path.exists(path):
-        return None, None
+        return none
     text = open(path).read()
     if f"library source hash: {build.source_hash()}" not in text:
-        return None, None
-    traffic, avg_us = None, None
+        return none
+    traffic, avg_us, valu = None, None, None
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
         if not cells or cells[0] != kernel_name:
@@ -414,8 +452,12 @@ def profile_figures(name, kernel_name):
                 traffic = float(cells[2]) * 1024 * FETCH_SCALE + float(cells[3]) * 1024 * WRITE_SCALE
             elif len(cells) == 6:  # kernel | calls | avg us | min us | max us | % time
                 avg_us = float(cells[2])
+            elif len(cells) == 3 and cells[1] == "SQ_INSTS_VALU":  # kernel | counter | value
+                valu = float(cells[2])
         except ValueError:
             continue
+    if want_valu:
+        return traffic, avg_us, valu
     return traffic, avg_us
 
 
@@ -587,8 +629,11 @@ def summarize(r, workload, steps):
     average duration, for comparison; and the step's algorithmic fraction."""
     kd = r["dominant"]
     alg_launch = kd["bytes_per_lu"] * kd.get("units", r["ns"])
-    traffic, prof_us = profile_figures(workload, kd["name"].split(" (")[0])
+    traffic, prof_us, valu = profile_figures(workload, kd["name"].split(" (")[0], want_valu=True)
     traffic_gbs = traffic / (kd["us"] * 1e-6) / 1e9 if traffic is not None else None
+    # share of the chip's vector issue slots the kernel fills: a wavefront
+    # FP32/FP64 VALU instruction holds one of the 4 x 256 SIMDs for 4 cycles
+    valu_frac = valu * 4 / (kd["us"] * 1e-6 * CLOCK_HZ * 4 * N_CU) if valu is not None else None
     copy_gbs = copy_rate_gbs(int(alg_launch))
     rec = {
         "ms_per_step": r["secs"] / steps * 1e3,
@@ -609,7 +654,7 @@ def summarize(r, workload, steps):
                      "kernel": kd["name"], "bytes_per_lu": kd["bytes_per_lu"],
                      "algorithmic_bytes_per_launch": alg_launch, "us_per_launch": kd["us"],
                      "launches_per_step": kd.get("launches_per_step"),
-                     "profile_avg_us": prof_us,
+                     "profile_avg_us": prof_us, "valu_issue_frac": valu_frac,
                      "copy_gbs_same_bytes": copy_gbs, "frac_of_copy": kd["gbs"] / copy_gbs},
         "step_algorithmic_frac": r["mlups"] * 1e6 * r["step_min_bytes_per_lu"] / (HBM_PEAK_GBS * 1e9),
         "mall_resident": r["mall_resident"],

@@ -64,10 +64,12 @@ def test_table1_spurious_velocities(hlb, row):
     assert 5 < vals["SC"] / vals["OC"] < 15
 
 
-def _centre_and_diameters(f, shape):
-    """Centre of mass of the nodes inside the drop (phi > 0) and the
-    horizontal and vertical diameters from the interpolated phi = 0
-    crossings through it."""
+def _shape_measures(f, shape):
+    """Centre of mass of the nodes inside the drop (phi > 0); the horizontal
+    and vertical diameters from the interpolated phi = 0 crossings through
+    it; the ratio sqrt(Ixx / Iyy) of the second moments of phi > 0 about the
+    centre (a shape measure that does not depend on the interface profile at
+    two points); and the fluid velocity there."""
     ph = f["phi"]
     ny, nx = shape
     wgt = np.clip(ph, 0, None)
@@ -86,8 +88,33 @@ def _centre_and_diameters(f, shape):
 
     dx = width(ph[int(round(cy)) % ny])
     dy = width(ph[:, int(round(cx)) % nx])
+    X = (np.arange(nx) - cx + nx / 2) % nx - nx / 2
+    Y = np.arange(ny) - cy
+    mom = np.sqrt((wgt * X[None, :] ** 2).sum() / (wgt * Y[:, None] ** 2).sum())
     ux = f["u"][0][int(round(cy)) % ny, int(round(cx)) % nx]
-    return cx, cy, dx, dy, ux
+    return cx, cy, dx / dy, mom, ux
+
+
+def _advected_drop(hlb, gx, kappa=PAPER["kappa"], t_end=3000):
+    prm = dict(PAPER, kappa=kappa)
+    w = np.sqrt(-2 * prm["kappa"] / prm["a"])
+    shape = (128, 256)
+    eq = hlb.Sim(shape, "f64", **prm, tau=1.0, N=0.3, Q=2.5)
+    eq.init(synth.drop(shape, 32, 1.0, w, center=(64, 128)))
+    eq.step(5000)
+    f0, p0 = eq.state()
+    eq.close()
+    sim = hlb.Sim(shape, "f64", **prm, tau=1.0, N=0.3, Q=2.5, g_ext=(gx, 0.0))
+    sim.set_state(f0, p0)
+    hist = []
+    for t in range(0, t_end + 1, 100):
+        if t == 500:
+            sim.set_params(**prm, tau=1.0, N=0.3, Q=2.5, g_ext=(0.0, 0.0))
+        hist.append((t,) + _shape_measures(sim.fields(), shape))
+        if t < t_end:
+            sim.step(100)
+    sim.close()
+    return np.array(hist), shape
 
 
 @pytest.mark.parametrize("gx", [1e-5, 3e-5, 5e-5])
@@ -95,37 +122,47 @@ def test_drop_advection_galilean(hlb, gx):
     """Sec. 3, drop advection: an equilibrated drop of diameter 64 in
     256 x 128, optimal stencil, body force G = n (g_x, 0) until t = 500.
     Afterwards the centre of mass moves with the fluid velocity at the
-    centre of mass (v_CM = v_f within 1%) and the drop stays round.  The
-    paper quotes a diameter ratio within 3% of 1 (without the time window)
-    and notes that faster drops stretch along x.  Measured here over
-    t <= 3000: 1.5% at g_x = 1e-5, 3.8% at 3e-5, 5.5% at 5e-5, so the bound is
-    3% at 1e-5 and grows with the speed (5% and 7%)."""
-    shape = (128, 256)
-    phi = synth.drop(shape, 32, 1.0, W, center=(64, 128))
-    eq = hlb.Sim(shape, "f64", **PAPER, tau=1.0, N=0.3, Q=2.5)
-    eq.init(phi)
-    eq.step(5000)
-    f0, p0 = eq.state()
-    eq.close()
-    sim = hlb.Sim(shape, "f64", **PAPER, tau=1.0, N=0.3, Q=2.5, g_ext=(gx, 0.0))
-    sim.set_state(f0, p0)
-    hist = []
-    for t in range(0, 3001, 100):
-        if t == 500:
-            sim.set_params(**PAPER, tau=1.0, N=0.3, Q=2.5, g_ext=(0.0, 0.0))
-        hist.append((t,) + _centre_and_diameters(sim.fields(), shape))
-        if t < 3000:
-            sim.step(100)
-    h = np.array(hist)
+    centre of mass (v_CM = v_f within 1%), and the fluid moves with the
+    momentum the force gave it.  The paper's shape statements are tested in
+    test_drop_advection_shape."""
+    h, shape = _advected_drop(hlb, gx)
     xs = np.unwrap(h[:, 1] * 2 * np.pi / shape[1]) * shape[1] / (2 * np.pi)
     vcm = np.diff(xs) / 100.0
     after = h[:, 0][1:] > 1000
     v_cm = vcm[after].mean()
     v_f = h[1:, 5][after].mean()
-    aspect = h[:, 3] / h[:, 4]
-    print(f"g_x={gx}: v_CM={v_cm:.5e} v_f={v_f:.5e} max|D_x/D_y - 1|={np.abs(aspect - 1).max():.4f} "
-          f"D_x/D_y every 500 steps: {np.round(aspect[::5], 4).tolist()}", flush=True)
+    print(f"g_x={gx}: v_CM={v_cm:.5e} v_f={v_f:.5e}; D_x/D_y - 1 every 500 steps "
+          f"{np.round(h[::5, 3] - 1, 4).tolist()}; moment ratio - 1 {np.round(h[::5, 4] - 1, 4).tolist()}",
+          flush=True)
     assert abs(v_cm / v_f - 1) < 0.01
     assert abs(v_f / (gx * 500) - 1) < 0.05  # momentum given by the force, n ~ 1
-    bound = {1e-5: 0.03, 3e-5: 0.05, 5e-5: 0.07}[gx]
-    assert np.abs(aspect - 1).max() < bound
+
+
+def test_drop_advection_shape(hlb):
+    """Sec. 3, drop advection, shape: the paper states that the diameter
+    ratio stays within 3% of 1, that a faster drop is slightly deformed, and
+    that the deformation becomes negligible with a larger surface tension
+    (larger kappa).  The paper gives neither the diameters' definition nor
+    the time window, so two definitions are used over t <= 3000: the phi = 0
+    crossings through the centre (D_x / D_y) and the second moments of
+    phi > 0 (sqrt(Ixx / Iyy)).
+      - At g_x = 1e-5 both stay within the paper's 3%.
+      - The deformation grows with the speed: at g_x = 1e-5, 3e-5, 5e-5 the
+        largest deviation of either measure increases.
+      - The second-moment deformation at g_x = 3e-5 drops by at least a
+        factor 2 when kappa is four times larger (the paper's remark); the
+        phi = 0 crossings do not respond to kappa, so their growth is a
+        property of the advected interface profile, not of the shape.
+    The g_x = 3e-5 deviations themselves (3.8% and 3.4%) exceed the quoted
+    3%; see the readings of the paper."""
+    dev = {}
+    for gx in (1e-5, 3e-5, 5e-5):
+        h, _ = _advected_drop(hlb, gx)
+        dev[gx] = (np.abs(h[:, 3] - 1).max(), np.abs(h[:, 4] - 1).max())
+    h4, _ = _advected_drop(hlb, 3e-5, kappa=4 * PAPER["kappa"])
+    dev_k4 = (np.abs(h4[:, 3] - 1).max(), np.abs(h4[:, 4] - 1).max())
+    print(f"max deviations (crossings, moments): {dev}; kappa x 4 at 3e-5: {dev_k4}", flush=True)
+    assert max(dev[1e-5]) < 0.03
+    for k in (0, 1):
+        assert dev[1e-5][k] < dev[3e-5][k] < dev[5e-5][k]
+    assert dev_k4[1] < 0.5 * dev[3e-5][1]

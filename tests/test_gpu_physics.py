@@ -226,3 +226,40 @@ def test_laplace_law_3d_r30_in_256(hlb):
     assert abs(ratio - 1) < 0.05
     assert abs(st["radius"] / 30 - 1) < 0.05
     sim.close()
+
+
+def test_laplace_law_with_the_expanded_force(hlb):
+    """Laplace's law with the default expanded force F = -[(a phi + 3 b phi^3)
+    grad phi - kappa phi grad lap phi] (the form the paper analyses in Sec. 3).
+    In the continuum it equals -phi grad mu, but its discrete form is not
+    zero where mu is uniform, so the density carries a force of order
+    (dx / w)^2 inside the interface (w = sqrt(-2 kappa / a)) and
+    Delta p R / sigma falls short of 1 by an amount of that order.  Measured
+    over 20,000 steps at the paper's parameters (w = sqrt(6), drops of radius
+    24 and 32 in 256^2) and 8000 steps at a = -0.1, kappa = 0.1 (w = sqrt(2),
+    radius 24 in 128^2): the shortfall is 0.9 (dx / w)^2 in all three, so it
+    is asserted within [0.7, 1.05] (dx / w)^2 -- a wrong bulk coefficient or
+    a dropped force term moves it out of that band.  The mu-first force,
+    whose discrete force vanishes where mu is uniform, is within 5% in every
+    case."""
+    paper = dict(a=-1e-3, b=1e-3, kappa=3e-3, gamma=5.0, tau=1.0)
+    short = {}
+    for label, prm, L, R, steps in (("paper", paper, 256, 32, 20000), ("paper24", paper, 256, 24, 20000),
+                                    ("base", BASE, 128, 24, 8000)):
+        a, b, kappa = prm["a"], prm["b"], prm["kappa"]
+        sigma = _sigma(a, b, kappa)
+        for ff in (1, 0):
+            sim = hlb.Sim((L, L), "f64", **prm, N=0.3, Q=2.5, force_form=ff)
+            sim.init(synth.drop((L, L), R, np.sqrt(-a / b), _w(a, kappa)))
+            sim.step(steps)
+            st = sim.drop_stats((L // 2, L // 2), R - 8, R + 12)
+            ratio = st["dp"] * st["radius"] / sigma
+            print(f"{label}: force form {'ii' if ff else 'i'}, R = {R}: Delta p R / sigma = {ratio:.4f}", flush=True)
+            if ff == 1:
+                short[label] = (1 - ratio) / (1.0 / _w(a, kappa) ** 2)
+            else:
+                assert abs(ratio - 1) < 0.05
+            sim.close()
+    print(f"shortfall / (dx / w)^2: {short}", flush=True)
+    for v in short.values():
+        assert 0.7 < v < 1.05
