@@ -50,17 +50,22 @@ int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // LDS bytes of the fused-tile substep kernel (two rotating arrays for phi, h
 // and the potential, and u*_x, u*_y, on the staged box of its geometry: rows
 // TO + 6M, columns TO plus a halo of 3M rounded up to 16-byte vectors on
-// each side, plus a vector of padding on each side), and a CU's LDS.
+// each side, rows back to back), and a CU's LDS.
 constexpr size_t kMaxLds = 163840;
 constexpr size_t fused_tile_lds(size_t es, int M, int TO) {
   const size_t V = 16 / es, H = 3 * M, HA = (H + V - 1) / V * V;
-  const size_t rows = TO + 2 * H, pitch = TO + 2 * HA + 2 * V;
+  const size_t rows = TO + 2 * H, pitch = TO + 2 * HA;
   return 4 * rows * pitch * es;
 }
 
-// The fixed-mapping fused tile (k_ch_tile2): LDS of its two arrays, and the
-// vectors of the staged box per thread, which stay in registers (at most 3).
-constexpr size_t fused_tile2_lds(size_t es, int M, int TO) { return fused_tile_lds(es, M, TO) / 2; }
+// The fixed-mapping fused tile (k_ch_tile2): LDS of its two arrays (rows
+// padded by a vector on each side), and the vectors of the staged box per
+// thread, which stay in registers (at most 3).
+constexpr size_t fused_tile2_lds(size_t es, int M, int TO) {
+  const size_t V = 16 / es, H = 3 * M, HA = (H + V - 1) / V * V;
+  const size_t rows = TO + 2 * H, pitch = TO + 2 * HA + 2 * V;
+  return 2 * rows * pitch * es;
+}
 constexpr int fused_tile2_items(size_t es, int M, int TO, int NTH) {
   const int V = 16 / (int)es, H = 3 * M, HA = (H + V - 1) / V * V;
   const int rows = TO + 2 * H, nq = (TO + 2 * HA) / V;

@@ -963,22 +963,25 @@ __global__ void __launch_bounds__(BW) k_chm_batch(const SimDesc *__restrict__ si
 // Geometry of the fused-tile kernel.  The staged box holds the tile plus a
 // halo of H = 3M rows; in x the halo is rounded up to whole 16-byte vectors
 // (HA), so that the box starts on a vector boundary of the lattice row and
-// is staged and stored with 16-byte accesses.  Rows have PITCH elements with
-// OFF leading ones, so that each vector of a row is aligned and the
-// neighbours at x - 1 and x + V of any vector of the box are inside the row.
-// Four arrays: two for phi, h and the diffusion potential, which rotate
-// (see k_ch_tile), and u*_x, u*_y.
+// is staged and stored with 16-byte accesses.  LDS is the bytes of
+// k_ch_tile's four arrays: two for phi, h and the diffusion potential, which
+// rotate (see k_ch_tile), and u*_x, u*_y.
 template <typename T, int M, int TO>
 struct FusedTileGeom {
   static constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte vector
   static constexpr int H = 3 * M;
   static constexpr int HA = (H + V - 1) / V * V;
-  static constexpr int DX = HA - H;     // column of the H-halo box's origin
   static constexpr int L0 = TO + 2 * H;  // staged rows
   static constexpr int LW = TO + 2 * HA;  // staged columns, a multiple of V
+  // k_ch_tile2 reads the west and east neighbours of every staged vector,
+  // including the first and last rows, so its rows carry a vector of padding
+  // on each side (column c at OFF + c).  k_ch_tile never reads past its
+  // rows' ends and stores rows back to back (pitch LW): a wavefront's
+  // consecutive items are then consecutive 16-byte vectors of LDS, which the
+  // 64 banks serve without conflicts.
   static constexpr int OFF = V;
   static constexpr int PITCH = LW + 2 * V;
-  static constexpr size_t LDS = 4ull * L0 * PITCH * sizeof(T);
+  static constexpr size_t LDS = 4ull * L0 * LW * sizeof(T);
 };
 
 // Rows [gy0, gy0 + NR) x columns [gx0, gx0 + NC * V) of a periodic 2D field
@@ -1060,12 +1063,15 @@ __device__ __forceinline__ T lane_shift(T v) {
 // to B, the potential overwrites phi^s in A (its phase reads phi only at
 // the site it writes) and phi^{s+1} overwrites h in B (likewise), after
 // which A and B swap roles.
-// A work item is V consecutive sites of a row (one 16-byte vector); item i
-// of a region with nq vectors per row is row i / nq, vector i % nq, and
-// thread t takes items t, t + NTH, ...  The vectors of a region are aligned
-// down, so the first and last of a row may extend past the region: those
-// sites are computed from stale values and written where nothing reads them
-// again (outside the region that the next phase reads).  The neighbour
+// A work item is V consecutive sites of a row (one 16-byte vector).  A phase
+// runs over whole staged rows of its row range, so item i of a phase is the
+// vector at offset r0 P + V i, and thread t takes items t, t + NTH, ...; the
+// sites it computes in columns outside the region use values from outside
+// the region and are never read by a site inside the next region.  Rows lie
+// back to back in LDS, so a wavefront's 64 items are 1 KiB of consecutive
+// LDS, read and written without bank conflicts.  (Regions of only their own
+// columns took 4% fewer instructions but made every row change inside a
+// wavefront a bank conflict, and ran slower.)  The neighbour
 // west (east) of a vector's first (last) site is the last (first) element
 // of the vector in the previous (next) lane, which holds the previous (next)
 // item of the same row, except at the start (end) of a row and at the
@@ -1079,7 +1085,8 @@ template <typename T, int M, int TO, bool FLUX, int NTH, bool LAP9>
 __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict__ phi_in, const T *__restrict__ u,
                                                  T *__restrict__ phi_out) {
   using G = FusedTileGeom<T, M, TO>;
-  constexpr int V = G::V, H = G::H, HA = G::HA, DX = G::DX, L0 = G::L0, LW = G::LW, OFF = G::OFF, P = G::PITCH;
+  constexpr int V = G::V, H = G::H, HA = G::HA, L0 = G::L0, LW = G::LW;
+  constexpr int P = LW, NQ = LW / V;  // row pitch (rows back to back) and vectors per row
   static_assert(NTH % 64 == 0, "items of a wavefront are consecutive");
   typedef T vec __attribute__((ext_vector_type(V)));
   __shared__ __attribute__((aligned(16))) T sA[L0 * P], sB[L0 * P], sux[L0 * P], suy[L0 * P];
@@ -1092,27 +1099,31 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
   // nx a multiple of V keeps every row start (and so every vector) aligned
   const bool whole = nx % V == 0 && aligned(phi_in) && aligned(u) && aligned(u + ns) && aligned(phi_out);
   {
-    RowStage<T, L0, LW / V, NTH> lphi, lux, luy;
+    RowStage<T, L0, NQ, NTH> lphi, lux, luy;
     lphi.issue(phi_in, nx, ny, x0 - HA, y0 - H, whole);
     lux.issue(u, nx, ny, x0 - HA, y0 - H, whole);
     luy.issue(u + ns, nx, ny, x0 - HA, y0 - H, whole);
-    lphi.template commit<P, OFF>(sA);
-    lux.template commit<P, OFF>(sux);
-    luy.template commit<P, OFF>(suy);
+    lphi.template commit<P, 0>(sA);
+    lux.template commit<P, 0>(sux);
+    luy.template commit<P, 0>(suy);
   }
   __syncthreads();
   const T dt = T(p.dt), dtg = T(p.dt) * T(p.gamma);
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cR = T(p.cR), cC = T(p.cC);
   const int lane = threadIdx.x & 63;
-  auto ld = [](const T *arr, int y, int x) { return *reinterpret_cast<const vec *>(arr + y * P + OFF + x); };
-  auto st = [](T *arr, int y, int x, vec v) { *reinterpret_cast<vec *>(arr + y * P + OFF + x) = v; };
+  // a work item is the vector at element offset o of an array; the rows above
+  // and below are at o - P and o + P
+  auto ld = [](const T *arr, int o) { return *reinterpret_cast<const vec *>(arr + o); };
+  auto st = [](T *arr, int o, vec v) { *reinterpret_cast<vec *>(arr + o) = v; };
   // the V-site neighbours to the west and east of the vector c of item i at
-  // (y, x) of arr, in a region of nq vectors per row.  Every lane issues the
-  // LDS load (lanes served by the shift read element 0, a broadcast), so no
-  // branch is formed around it.
-  auto west = [&](const T *arr, vec c, int y, int x, int i, int nq) {
-    const bool far = i % nq == 0 || lane == 0;
-    const T l = arr[far ? y * P + OFF + x - 1 : 0];
+  // offset o of arr.  Every lane issues the LDS load (lanes served by the
+  // shift read element 0, a broadcast), so no branch is formed around it.
+  // At a row's first (last) vector the element read is the last (first) of
+  // the neighbouring row: a value outside the region, used only by sites
+  // outside it.
+  auto west = [&](const T *arr, vec c, int o, int i) {
+    const bool far = i % NQ == 0 || lane == 0;
+    const T l = arr[far ? o - 1 : 0];
     const T d = lane_shift<-1>(c[V - 1]);
     vec r;
     r[0] = far ? l : d;
@@ -1120,9 +1131,9 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     for (int j = 1; j < V; j++) r[j] = c[j - 1];
     return r;
   };
-  auto east = [&](const T *arr, vec c, int y, int x, int i, int nq) {
-    const bool far = i % nq == nq - 1 || lane == 63;
-    const T l = arr[far ? y * P + OFF + x + V : 0];
+  auto east = [&](const T *arr, vec c, int o, int i) {
+    const bool far = i % NQ == NQ - 1 || lane == 63;
+    const T l = arr[far ? o + V : 0];
     const T d = lane_shift<+1>(c[0]);
     vec r;
 #pragma unroll
@@ -1130,15 +1141,16 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     r[V - 1] = far ? l : d;
     return r;
   };
-  // items of a region: rows [r0, r1), columns DX + [r0, r1) widened to whole vectors
+  // the items of rows [r0, r1): whole staged rows, item i at offset
+  // r0 P + V i.  Rows r0 - 1 and r1 are inside the box (r0 >= 1, r1 <= L0 - 1).
   auto region = [](auto R0, auto R1, auto body) {
     constexpr int r0 = decltype(R0)::value, r1 = decltype(R1)::value;
-    constexpr int xa = ((DX + r0) / V) * V, nq = (DX + r1 - xa + V - 1) / V;
-    constexpr int N = (r1 - r0) * nq, K = (N + NTH - 1) / NTH;
+    static_assert(r0 >= 1 && r1 <= L0 - 1, "neighbour rows inside the staged box");
+    constexpr int N = (r1 - r0) * NQ, K = (N + NTH - 1) / NTH;
 #pragma unroll
     for (int k = 0; k < K; k++) {
       const int i = threadIdx.x + k * NTH;
-      if (N % NTH == 0 || i < N) body(r0 + i / nq, xa + V * (i % nq), i, nq);
+      if (N % NTH == 0 || i < N) body(r0 * P + V * i, i);
     }
   };
   using std::integral_constant;
@@ -1149,91 +1161,87 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     T *const sq = s % 2 == 0 ? sB : sA;  // h, then phi^{s+1}
     constexpr int lo = 3 * s;
     // h on rows [lo + 1, L0 - lo - 1)
-    region(integral_constant<int, lo + 1>{}, integral_constant<int, L0 - lo - 1>{},
-           [&](int y, int x, int i, int nq) {
-             const vec pc = ld(sp, y, x), pdn = ld(sp, y - 1, x), pup = ld(sp, y + 1, x);
-             const vec uxc = ld(sux, y, x);
-             const vec uyc = ld(suy, y, x), uyd = ld(suy, y - 1, x), uyu = ld(suy, y + 1, x);
-             const vec pw = west(sp, pc, y, x, i, nq), pe = east(sp, pc, y, x, i, nq);
-             const vec uxw = west(sux, uxc, y, x, i, nq), uxe = east(sux, uxc, y, x, i, nq);
-             vec h;
+    region(integral_constant<int, lo + 1>{}, integral_constant<int, L0 - lo - 1>{}, [&](int o, int i) {
+      const vec pc = ld(sp, o), pdn = ld(sp, o - P), pup = ld(sp, o + P);
+      const vec uxc = ld(sux, o);
+      const vec uyc = ld(suy, o), uyd = ld(suy, o - P), uyu = ld(suy, o + P);
+      const vec pw = west(sp, pc, o, i), pe = east(sp, pc, o, i);
+      const vec uxw = west(sux, uxc, o, i), uxe = east(sux, uxc, o, i);
+      vec h;
 #pragma unroll
-             for (int j = 0; j < V; j++) {
-               T rhs;
-               if constexpr (!FLUX) {
-                 const T tx =
-                     pc[j] * ((uxe[j] - uxw[j]) * T(0.5)) + uxc[j] * (uxc[j] > T(0) ? pc[j] - pw[j] : pe[j] - pc[j]);
-                 const T ty = pc[j] * ((uyu[j] - uyd[j]) * T(0.5)) +
-                              uyc[j] * (uyc[j] > T(0) ? pc[j] - pdn[j] : pup[j] - pc[j]);
-                 rhs = tx + ty;
-               } else {
-                 const T vxe = (uxc[j] + uxe[j]) * T(0.5), vxw = (uxw[j] + uxc[j]) * T(0.5);
-                 const T vyu = (uyc[j] + uyu[j]) * T(0.5), vyd = (uyd[j] + uyc[j]) * T(0.5);
-                 const T tx = (vxe > T(0) ? vxe * pc[j] : vxe * pe[j]) - (vxw > T(0) ? vxw * pw[j] : vxw * pc[j]);
-                 const T ty =
-                     (vyu > T(0) ? vyu * pc[j] : vyu * pup[j]) - (vyd > T(0) ? vyd * pdn[j] : vyd * pc[j]);
-                 rhs = tx + ty;
-               }
-               h[j] = pc[j] - dt * rhs;
-             }
-             st(sq, y, x, h);
-           });
+      for (int j = 0; j < V; j++) {
+        T rhs;
+        if constexpr (!FLUX) {
+          const T tx =
+              pc[j] * ((uxe[j] - uxw[j]) * T(0.5)) + uxc[j] * (uxc[j] > T(0) ? pc[j] - pw[j] : pe[j] - pc[j]);
+          const T ty =
+              pc[j] * ((uyu[j] - uyd[j]) * T(0.5)) + uyc[j] * (uyc[j] > T(0) ? pc[j] - pdn[j] : pup[j] - pc[j]);
+          rhs = tx + ty;
+        } else {
+          const T vxe = (uxc[j] + uxe[j]) * T(0.5), vxw = (uxw[j] + uxc[j]) * T(0.5);
+          const T vyu = (uyc[j] + uyu[j]) * T(0.5), vyd = (uyd[j] + uyc[j]) * T(0.5);
+          const T tx = (vxe > T(0) ? vxe * pc[j] : vxe * pe[j]) - (vxw > T(0) ? vxw * pw[j] : vxw * pc[j]);
+          const T ty = (vyu > T(0) ? vyu * pc[j] : vyu * pup[j]) - (vyd > T(0) ? vyd * pdn[j] : vyd * pc[j]);
+          rhs = tx + ty;
+        }
+        h[j] = pc[j] - dt * rhs;
+      }
+      st(sq, o, h);
+    });
     __syncthreads();
     // diffusion potential on [lo + 2, L0 - lo - 2), over phi^s
-    region(integral_constant<int, lo + 2>{}, integral_constant<int, L0 - lo - 2>{},
-           [&](int y, int x, int i, int nq) {
-             const vec hc = ld(sq, y, x), hdn = ld(sq, y - 1, x), hup = ld(sq, y + 1, x);
-             const vec ph = ld(sp, y, x);
-             const vec hw = west(sq, hc, y, x, i, nq), he = east(sq, hc, y, x, i, nq);
-             vec dg;  // sums of the diagonal neighbours
-             if constexpr (LAP9) {
-               const vec dw = west(sq, hdn, y - 1, x, i, nq), de = east(sq, hdn, y - 1, x, i, nq);
-               const vec uw = west(sq, hup, y + 1, x, i, nq), ue = east(sq, hup, y + 1, x, i, nq);
+    region(integral_constant<int, lo + 2>{}, integral_constant<int, L0 - lo - 2>{}, [&](int o, int i) {
+      const vec hc = ld(sq, o), hdn = ld(sq, o - P), hup = ld(sq, o + P);
+      const vec ph = ld(sp, o);
+      const vec hw = west(sq, hc, o, i), he = east(sq, hc, o, i);
+      vec dg;  // sums of the diagonal neighbours
+      if constexpr (LAP9) {
+        const vec dw = west(sq, hdn, o - P, i), de = east(sq, hdn, o - P, i);
+        const vec uw = west(sq, hup, o + P, i), ue = east(sq, hup, o + P, i);
 #pragma unroll
-               for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
-             }
-             vec mu;
+        for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
+      }
+      vec mu;
 #pragma unroll
-             for (int j = 0; j < V; j++) {
-               T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
-               if constexpr (LAP9) Lh += cR * dg[j];
-               mu[j] = a * hc[j] + b * ph[j] * ph[j] * ph[j] - kappa * Lh;
-             }
-             st(sp, y, x, mu);
-           });
+      for (int j = 0; j < V; j++) {
+        T Lh = cQ * ((he[j] + hw[j]) + (hup[j] + hdn[j])) + cC * hc[j];
+        if constexpr (LAP9) Lh += cR * dg[j];
+        mu[j] = a * hc[j] + b * ph[j] * ph[j] * ph[j] - kappa * Lh;
+      }
+      st(sp, o, mu);
+    });
     __syncthreads();
     // phi^{s+1} on [lo + 3, L0 - lo - 3), over h
-    region(integral_constant<int, lo + 3>{}, integral_constant<int, L0 - lo - 3>{},
-           [&](int y, int x, int i, int nq) {
-             const vec mc = ld(sp, y, x), mdn = ld(sp, y - 1, x), mup = ld(sp, y + 1, x);
-             const vec hc = ld(sq, y, x);
-             const vec mw = west(sp, mc, y, x, i, nq), me = east(sp, mc, y, x, i, nq);
-             vec dg;
-             if constexpr (LAP9) {
-               const vec dw = west(sp, mdn, y - 1, x, i, nq), de = east(sp, mdn, y - 1, x, i, nq);
-               const vec uw = west(sp, mup, y + 1, x, i, nq), ue = east(sp, mup, y + 1, x, i, nq);
+    region(integral_constant<int, lo + 3>{}, integral_constant<int, L0 - lo - 3>{}, [&](int o, int i) {
+      const vec mc = ld(sp, o), mdn = ld(sp, o - P), mup = ld(sp, o + P);
+      const vec hc = ld(sq, o);
+      const vec mw = west(sp, mc, o, i), me = east(sp, mc, o, i);
+      vec dg;
+      if constexpr (LAP9) {
+        const vec dw = west(sp, mdn, o - P, i), de = east(sp, mdn, o - P, i);
+        const vec uw = west(sp, mup, o + P, i), ue = east(sp, mup, o + P, i);
 #pragma unroll
-               for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
-             }
-             vec out;
+        for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
+      }
+      vec out;
 #pragma unroll
-             for (int j = 0; j < V; j++) {
-               T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
-               if constexpr (LAP9) Lm += cR * dg[j];
-               out[j] = hc[j] + dtg * Lm;
-             }
-             st(sq, y, x, out);
-           });
+      for (int j = 0; j < V; j++) {
+        T Lm = cQ * ((me[j] + mw[j]) + (mup[j] + mdn[j])) + cC * mc[j];
+        if constexpr (LAP9) Lm += cR * dg[j];
+        out[j] = hc[j] + dtg * Lm;
+      }
+      st(sq, o, out);
+    });
     __syncthreads();
   });
   // phi^M is in B after an odd number of substeps, else in A
   const T *res = M % 2 == 1 ? sB : sA;
-  constexpr int NQ = TO / V;
-  for (int i = threadIdx.x; i < TO * NQ; i += NTH) {
-    const int ty = i / NQ, tx = V * (i % NQ);
+  constexpr int NO = TO / V;
+  for (int i = threadIdx.x; i < TO * NO; i += NTH) {
+    const int ty = i / NO, tx = V * (i % NO);
     const int x = x0 + tx, y = y0 + ty;
     if (y >= ny) continue;
-    const vec v = ld(res, H + ty, HA + tx);
+    const vec v = ld(res, (H + ty) * P + HA + tx);
     if (whole) {
       if (x < nx) *reinterpret_cast<vec *>(phi_out + (size_t)nx * y + x) = v;
     } else {
