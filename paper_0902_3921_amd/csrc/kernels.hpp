@@ -1070,14 +1070,13 @@ __device__ __forceinline__ T lane_shift(T v) {
 // the region and are never read by a site inside the next region.  Rows lie
 // back to back in LDS, so a wavefront's 64 items are 1 KiB of consecutive
 // LDS, read and written without bank conflicts.  (Regions of only their own
-// columns took 4% fewer instructions but made every row change inside a
+// columns took fewer instructions but made every row change inside a
 // wavefront a bank conflict, and ran slower.)  The neighbour
 // west (east) of a vector's first (last) site is the last (first) element
 // of the vector in the previous (next) lane, which holds the previous (next)
-// item of the same row, except at the start (end) of a row and at the
-// edges of the wavefront: there it is read from LDS.  The same holds for the
-// rows above and below, whose edge values are the 9-point Laplacian's
-// diagonal neighbours.  Every phase loop has
+// item, except at the edges of the wavefront: there it is read from LDS.
+// The same holds for the rows above and below, whose edge values are the
+// 9-point Laplacian's diagonal neighbours.  Every phase loop has
 // a constant trip count and is unrolled, so that one item's loads can be
 // issued under another's arithmetic.
 // NTH threads per block (256, 512 or 1024).
@@ -1115,14 +1114,16 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
   // and below are at o - P and o + P
   auto ld = [](const T *arr, int o) { return *reinterpret_cast<const vec *>(arr + o); };
   auto st = [](T *arr, int o, vec v) { *reinterpret_cast<vec *>(arr + o) = v; };
-  // the V-site neighbours to the west and east of the vector c of item i at
-  // offset o of arr.  Every lane issues the LDS load (lanes served by the
-  // shift read element 0, a broadcast), so no branch is formed around it.
-  // At a row's first (last) vector the element read is the last (first) of
-  // the neighbouring row: a value outside the region, used only by sites
-  // outside it.
-  auto west = [&](const T *arr, vec c, int o, int i) {
-    const bool far = i % NQ == 0 || lane == 0;
+  // the V-site neighbours to the west and east of the vector c at offset o of
+  // arr: the neighbouring element is the last (first) of the previous (next)
+  // item, held by the previous (next) lane, and read from LDS only at the
+  // edges of the wavefront.  Every lane issues that LDS load (the others read
+  // element 0, a broadcast), so no branch is formed around it.  At a row's
+  // first (last) vector this is the last (first) element of the neighbouring
+  // row: it feeds only the site in staged column 0 (LW - 1), which lies
+  // outside every region.
+  auto west = [&](const T *arr, vec c, int o) {
+    const bool far = lane == 0;
     const T l = arr[far ? o - 1 : 0];
     const T d = lane_shift<-1>(c[V - 1]);
     vec r;
@@ -1131,8 +1132,8 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     for (int j = 1; j < V; j++) r[j] = c[j - 1];
     return r;
   };
-  auto east = [&](const T *arr, vec c, int o, int i) {
-    const bool far = i % NQ == NQ - 1 || lane == 63;
+  auto east = [&](const T *arr, vec c, int o) {
+    const bool far = lane == 63;
     const T l = arr[far ? o + V : 0];
     const T d = lane_shift<+1>(c[0]);
     vec r;
@@ -1150,7 +1151,7 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
 #pragma unroll
     for (int k = 0; k < K; k++) {
       const int i = threadIdx.x + k * NTH;
-      if (N % NTH == 0 || i < N) body(r0 * P + V * i, i);
+      if (N % NTH == 0 || i < N) body(r0 * P + V * i);
     }
   };
   using std::integral_constant;
@@ -1161,12 +1162,12 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     T *const sq = s % 2 == 0 ? sB : sA;  // h, then phi^{s+1}
     constexpr int lo = 3 * s;
     // h on rows [lo + 1, L0 - lo - 1)
-    region(integral_constant<int, lo + 1>{}, integral_constant<int, L0 - lo - 1>{}, [&](int o, int i) {
+    region(integral_constant<int, lo + 1>{}, integral_constant<int, L0 - lo - 1>{}, [&](int o) {
       const vec pc = ld(sp, o), pdn = ld(sp, o - P), pup = ld(sp, o + P);
       const vec uxc = ld(sux, o);
       const vec uyc = ld(suy, o), uyd = ld(suy, o - P), uyu = ld(suy, o + P);
-      const vec pw = west(sp, pc, o, i), pe = east(sp, pc, o, i);
-      const vec uxw = west(sux, uxc, o, i), uxe = east(sux, uxc, o, i);
+      const vec pw = west(sp, pc, o), pe = east(sp, pc, o);
+      const vec uxw = west(sux, uxc, o), uxe = east(sux, uxc, o);
       vec h;
 #pragma unroll
       for (int j = 0; j < V; j++) {
@@ -1190,14 +1191,14 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     });
     __syncthreads();
     // diffusion potential on [lo + 2, L0 - lo - 2), over phi^s
-    region(integral_constant<int, lo + 2>{}, integral_constant<int, L0 - lo - 2>{}, [&](int o, int i) {
+    region(integral_constant<int, lo + 2>{}, integral_constant<int, L0 - lo - 2>{}, [&](int o) {
       const vec hc = ld(sq, o), hdn = ld(sq, o - P), hup = ld(sq, o + P);
       const vec ph = ld(sp, o);
-      const vec hw = west(sq, hc, o, i), he = east(sq, hc, o, i);
+      const vec hw = west(sq, hc, o), he = east(sq, hc, o);
       vec dg;  // sums of the diagonal neighbours
       if constexpr (LAP9) {
-        const vec dw = west(sq, hdn, o - P, i), de = east(sq, hdn, o - P, i);
-        const vec uw = west(sq, hup, o + P, i), ue = east(sq, hup, o + P, i);
+        const vec dw = west(sq, hdn, o - P), de = east(sq, hdn, o - P);
+        const vec uw = west(sq, hup, o + P), ue = east(sq, hup, o + P);
 #pragma unroll
         for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
       }
@@ -1212,14 +1213,14 @@ __global__ void __launch_bounds__(NTH) k_ch_tile(KParams p, const T *__restrict_
     });
     __syncthreads();
     // phi^{s+1} on [lo + 3, L0 - lo - 3), over h
-    region(integral_constant<int, lo + 3>{}, integral_constant<int, L0 - lo - 3>{}, [&](int o, int i) {
+    region(integral_constant<int, lo + 3>{}, integral_constant<int, L0 - lo - 3>{}, [&](int o) {
       const vec mc = ld(sp, o), mdn = ld(sp, o - P), mup = ld(sp, o + P);
       const vec hc = ld(sq, o);
-      const vec mw = west(sp, mc, o, i), me = east(sp, mc, o, i);
+      const vec mw = west(sp, mc, o), me = east(sp, mc, o);
       vec dg;
       if constexpr (LAP9) {
-        const vec dw = west(sp, mdn, o - P, i), de = east(sp, mdn, o - P, i);
-        const vec uw = west(sp, mup, o + P, i), ue = east(sp, mup, o + P, i);
+        const vec dw = west(sp, mdn, o - P), de = east(sp, mdn, o - P);
+        const vec uw = west(sp, mup, o + P), ue = east(sp, mup, o + P);
 #pragma unroll
         for (int j = 0; j < V; j++) dg[j] = (ue[j] + uw[j]) + (de[j] + dw[j]);
       }
