@@ -224,6 +224,8 @@ def run_gpu(name, steps, warmup, plan=None, profile_mode=False, variants=True):
 
     lb_b, ch_b, step_b = algorithmic_bytes(d, q, es)
     seq = launch_sequence(m, plan)
+    if len(seq) == 1:
+        us_first = us_ch_step  # the step's only substep launch: its in-step time, unscaled
     n_first = sum(1 for k in seq if k == seq[0])
     # the dominant kernel: the instantiation with the most device time per step
     per_step = {"lb": us_lb, "ch": us_first * n_first}
