@@ -266,11 +266,13 @@ hlb_status hlb_step_timed(hlb_ctx *ctx, long long nsteps, double ms[2]);
 hlb_status hlb_set_plan(hlb_ctx *ctx, const int plan[4]);
 hlb_status hlb_get_plan(const hlb_ctx *ctx, int plan[4]);
 
-/* Times the candidate plans on the current state (each candidate runs all
- * the convection-diffusion substeps of a step from the current phi into
- * scratch buffers in the staging area, so the state is unchanged), keeps the
- * fastest and writes its time per substep in microseconds to *best_us (may
- * be NULL).  Synchronises. */
+/* Times the candidate plans on the current state, keeps the fastest and
+ * writes its time per substep in microseconds to *best_us (may be NULL).
+ * Each candidate runs as in a step: a collide-and-stream launch (which writes
+ * the spare population buffer and u* of the current state), then all the
+ * convection-diffusion substeps of a step from the current phi into scratch
+ * buffers in the staging area; the collide-and-stream time is subtracted.
+ * The state is unchanged.  Synchronises. */
 hlb_status hlb_autotune(hlb_ctx *ctx, double *best_us);
 
 /* Name of a device kernel as profiler traces print it (the full template

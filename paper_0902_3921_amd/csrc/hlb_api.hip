@@ -58,14 +58,9 @@ constexpr size_t fused_tile_lds(size_t es, int M, int TO) {
   return 4 * rows * pitch * es;
 }
 
-// The fixed-mapping fused tile (k_ch_tile2): LDS of its two arrays (rows
-// padded by a vector on each side), and the vectors of the staged box per
-// thread, which stay in registers (at most 3).
-constexpr size_t fused_tile2_lds(size_t es, int M, int TO) {
-  const size_t V = 16 / es, H = 3 * M, HA = (H + V - 1) / V * V;
-  const size_t rows = TO + 2 * H, pitch = TO + 2 * HA + 2 * V;
-  return 2 * rows * pitch * es;
-}
+// The fixed-mapping fused tile (k_ch_tile2): LDS of its two arrays, and the
+// vectors of the staged box per thread, which stay in registers (at most 3).
+constexpr size_t fused_tile2_lds(size_t es, int M, int TO) { return fused_tile_lds(es, M, TO) / 2; }
 constexpr int fused_tile2_items(size_t es, int M, int TO, int NTH) {
   const int V = 16 / (int)es, H = 3 * M, HA = (H + V - 1) / V * V;
   const int rows = TO + 2 * H, nq = (TO + 2 * HA) / V;
@@ -1506,30 +1501,43 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   const ChPlan saved = c->plan;
   double best = 1e300;
   ChPlan best_pl = saved;
-  for (const ChPlan &pl : cand) {
-    c->plan = pl;
-    float tmin = 1e30f;
+  // Each candidate is timed as it runs in a step: after a collide-and-stream
+  // launch, whose end (the write-back of its output) the first substep launch
+  // waits for.  That launch reads the current populations and phi and writes
+  // the spare population buffer and u* (u* of the current state, which the
+  // substeps then read), so repeating it leaves the state as it was.  The
+  // substeps run from the current phi into two scratch buffers in the staging
+  // area.  The collide-and-stream launch alone is timed first and subtracted.
+  auto timed = [&](bool with_substeps, float &tmin) {
+    tmin = 1e30f;
     for (int rep = 0; rep < 4; rep++) {
       (void)hipEventRecord(e0, c->stream);
-      // all substeps of a step, from the current phi into two scratch buffers
-      // in the staging area (the state is not touched)
       dispatch(c, [&](auto ops) {
         using T = typename decltype(ops)::Type;
         T *scratch = at<T>(c, c->lay.io);
-        ops.substeps(c, k, at<T>(c, c->lay.phi[c->phicur]), scratch, scratch + c->ns);
+        ops.lb(c, k);
+        if (with_substeps) ops.substeps(c, k, at<T>(c, c->lay.phi[c->phicur]), scratch, scratch + c->ns);
       });
       (void)hipEventRecord(e1, c->stream);
-      s = launch_check(c, "autotune launch");
-      if (s == HLB_OK) s = sync(c);
-      if (s != HLB_OK) break;
+      hlb_status r = launch_check(c, "autotune launch");
+      if (r == HLB_OK) r = sync(c);
+      if (r != HLB_OK) return r;
       float t = 0;
       (void)hipEventElapsedTime(&t, e0, e1);
       if (rep > 0) tmin = std::min(tmin, t);  // the first run warms up
     }
+    return HLB_OK;
+  };
+  float t_lb = 0;
+  s = timed(false, t_lb);
+  for (const ChPlan &pl : cand) {
     if (s != HLB_OK) break;
-    const double us_per_substep = tmin * 1e3 / c->m;
-    if (us_per_substep < best) {
-      best = us_per_substep;
+    c->plan = pl;
+    float tmin = 0;
+    s = timed(true, tmin);
+    if (s != HLB_OK) break;
+    if (tmin < best) {
+      best = tmin;
       best_pl = pl;
     }
   }
@@ -1537,7 +1545,7 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   (void)hipEventDestroy(e1);
   c->plan = s == HLB_OK ? best_pl : saved;
   c->plan_user = s == HLB_OK;
-  if (best_us) *best_us = best;
+  if (best_us) *best_us = s == HLB_OK ? std::max(0.0, best - double(t_lb)) * 1e3 / c->m : 0.0;
   return s;
 }
 

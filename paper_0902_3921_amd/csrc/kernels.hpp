@@ -973,14 +973,9 @@ struct FusedTileGeom {
   static constexpr int HA = (H + V - 1) / V * V;
   static constexpr int L0 = TO + 2 * H;  // staged rows
   static constexpr int LW = TO + 2 * HA;  // staged columns, a multiple of V
-  // k_ch_tile2 reads the west and east neighbours of every staged vector,
-  // including the first and last rows, so its rows carry a vector of padding
-  // on each side (column c at OFF + c).  k_ch_tile never reads past its
-  // rows' ends and stores rows back to back (pitch LW): a wavefront's
-  // consecutive items are then consecutive 16-byte vectors of LDS, which the
-  // 64 banks serve without conflicts.
-  static constexpr int OFF = V;
-  static constexpr int PITCH = LW + 2 * V;
+  // Rows lie back to back in LDS (pitch LW): a wavefront's consecutive items
+  // are then consecutive 16-byte vectors of LDS, which the 64 banks serve
+  // without conflicts.
   static constexpr size_t LDS = 4ull * L0 * LW * sizeof(T);
 };
 
@@ -1261,7 +1256,7 @@ struct FusedTile2 {
   static constexpr int NQ = G::LW / G::V;  // vectors per staged row
   static constexpr int NI = G::L0 * NQ;    // vectors of the staged box
   static constexpr int K = (NI + NTH - 1) / NTH;
-  static constexpr size_t LDS = 2ull * G::L0 * G::PITCH * sizeof(T);
+  static constexpr size_t LDS = 2ull * G::L0 * G::LW * sizeof(T);
 };
 
 // M convection-diffusion substeps of a TO x TO tile in one launch, like
@@ -1270,7 +1265,7 @@ struct FusedTile2 {
 // whole launch.  A phase reads the thread's own vector and the rows above
 // and below from LDS; the east and west neighbours come from the
 // neighbouring lanes (which own the neighbouring vectors of the row) by a
-// DPP shift, and from LDS at row ends and wavefront edges.  u* is fixed over
+// DPP shift, and from LDS at the wavefront's edges.  u* is fixed over
 // the substeps, so the advection half-step of each site is written once, in
 // registers, as five coefficients,
 //   h = c0 phi + cW phi_W + cE phi_E + cS phi_S + cN phi_N,
@@ -1286,7 +1281,7 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
                                                   T *__restrict__ phi_out) {
   using G = FusedTileGeom<T, M, TO>;
   using F2 = FusedTile2<T, M, TO, NTH>;
-  constexpr int V = G::V, H = G::H, HA = G::HA, L0 = G::L0, OFF = G::OFF, P = G::PITCH;
+  constexpr int V = G::V, H = G::H, HA = G::HA, L0 = G::L0, P = G::LW;  // rows back to back
   constexpr int NQ = F2::NQ, NI = F2::NI, K = F2::K;
   static_assert(NTH % 64 == 0, "vectors of a wavefront are consecutive");
   typedef T vec __attribute__((ext_vector_type(V)));
@@ -1300,11 +1295,16 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
   const bool whole = nx % V == 0 && aligned(phi_in) && aligned(u) && aligned(u + ns) && aligned(phi_out);
   const bool one = nx >= G::LW && ny >= L0;  // the box wraps at most once per axis
   const int lane = threadIdx.x & 63;
-  auto ld = [](const T *arr, int y, int x) { return *reinterpret_cast<const vec *>(arr + y * P + OFF + x); };
-  auto st = [](T *arr, int y, int x, vec v) { *reinterpret_cast<vec *>(arr + y * P + OFF + x) = v; };
-  auto west = [&](const T *arr, vec c, int y, int x, int i) {
-    const bool far = i % NQ == 0 || lane == 0;
-    const T l = arr[far ? y * P + OFF + x - 1 : 0];
+  auto ld = [](const T *arr, int y, int x) { return *reinterpret_cast<const vec *>(arr + y * P + x); };
+  auto st = [](T *arr, int y, int x, vec v) { *reinterpret_cast<vec *>(arr + y * P + x) = v; };
+  // the neighbouring element comes from the neighbouring lane, which holds
+  // the previous (next) vector of the box, and from LDS at the wavefront's
+  // edges.  At a row's first (last) vector it is the last (first) element of
+  // the neighbouring row (clamped to the box at its first and last vector):
+  // it feeds only the site in staged column 0 (LW - 1), outside every region.
+  auto west = [&](const T *arr, vec c, int y, int x) {
+    const bool far = lane == 0;
+    const T l = arr[far ? max(y * P + x - 1, 0) : 0];
     const T d = lane_shift<-1>(c[V - 1]);
     vec r;
     r[0] = far ? l : d;
@@ -1312,9 +1312,9 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
     for (int j = 1; j < V; j++) r[j] = c[j - 1];
     return r;
   };
-  auto east = [&](const T *arr, vec c, int y, int x, int i) {
-    const bool far = i % NQ == NQ - 1 || lane == 63;
-    const T l = arr[far ? y * P + OFF + x + V : 0];
+  auto east = [&](const T *arr, vec c, int y, int x) {
+    const bool far = lane == 63;
+    const T l = arr[far ? min(y * P + x + V, L0 * P - 1) : 0];
     const T d = lane_shift<+1>(c[0]);
     vec r;
 #pragma unroll
@@ -1367,7 +1367,7 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
       // every lane of a wavefront takes part in the shifts; rows without
       // both neighbours in the box only produce unused coefficients
       const vec uxc = ld(sA, r, x);
-      const vec uw = west(sA, uxc, r, x, i), ue = east(sA, uxc, r, x, i);
+      const vec uw = west(sA, uxc, r, x), ue = east(sA, uxc, r, x);
       if ((NI % NTH == 0 || i < NI) && r >= 1 && r < L0 - 1) {
         const vec uyc = ld(sB, r, x), un = ld(sB, r + 1, x), us = ld(sB, r - 1, x);
 #pragma unroll
@@ -1410,9 +1410,9 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
   const T a = T(p.a), b = T(p.b), kappa = T(p.kappa), cQ = T(p.cQ), cR = T(p.cR), cC = T(p.cC);
   // the sums of the four diagonal neighbours of a vector with rows n (above)
   // and s (below) of array arr
-  auto diag = [&](const T *arr, vec n, vec s, int r, int x, int i) {
-    const vec nw = west(arr, n, r + 1, x, i), ne = east(arr, n, r + 1, x, i);
-    const vec sw = west(arr, s, r - 1, x, i), se = east(arr, s, r - 1, x, i);
+  auto diag = [&](const T *arr, vec n, vec s, int r, int x) {
+    const vec nw = west(arr, n, r + 1, x), ne = east(arr, n, r + 1, x);
+    const vec sw = west(arr, s, r - 1, x), se = east(arr, s, r - 1, x);
     vec dg;
 #pragma unroll
     for (int j = 0; j < V; j++) dg[j] = (ne[j] + nw[j]) + (se[j] + sw[j]);
@@ -1432,7 +1432,7 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
       if (k * NTH + NTH - 1 < (lo + 1) * NQ || k * NTH >= (L0 - lo - 1) * NQ) continue;  // no row of this slot
       const bool in = (NI % NTH == 0 || i < NI) && r >= lo + 1 && r < L0 - lo - 1;
       const vec pc = ld(sp, r, x);
-      const vec pw = west(sp, pc, r, x, i), pe = east(sp, pc, r, x, i);
+      const vec pw = west(sp, pc, r, x), pe = east(sp, pc, r, x);
       if (in) {
         const vec pn = ld(sp, r + 1, x), ps = ld(sp, r - 1, x);
         vec hv;
@@ -1453,10 +1453,10 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
       if (k * NTH + NTH - 1 < (lo + 2) * NQ || k * NTH >= (L0 - lo - 2) * NQ) continue;
       const bool in = (NI % NTH == 0 || i < NI) && r >= lo + 2 && r < L0 - lo - 2;
       const vec hc = ld(sq, r, x);
-      const vec hw = west(sq, hc, r, x, i), he = east(sq, hc, r, x, i);
+      const vec hw = west(sq, hc, r, x), he = east(sq, hc, r, x);
       const vec hn = ld(sq, in ? r + 1 : 0, x), hs = ld(sq, in ? r - 1 : 0, x);
       vec dg;
-      if constexpr (LAP9) dg = diag(sq, hn, hs, in ? r : 1, x, i);
+      if constexpr (LAP9) dg = diag(sq, hn, hs, in ? r : 1, x);
       if (in) {
         const vec pc = ld(sp, r, x);  // phi^s at this vector, overwritten below
         vec pt;
@@ -1480,10 +1480,10 @@ __global__ void __launch_bounds__(NTH) k_ch_tile2(KParams p, const T *__restrict
       if (k * NTH + NTH - 1 < (lo + 3) * NQ || k * NTH >= (L0 - lo - 3) * NQ) continue;
       const bool in = (NI % NTH == 0 || i < NI) && r >= lo + 3 && r < L0 - lo - 3;
       const vec mc = ld(sp, r, x);
-      const vec mw = west(sp, mc, r, x, i), me = east(sp, mc, r, x, i);
+      const vec mw = west(sp, mc, r, x), me = east(sp, mc, r, x);
       const vec mn = ld(sp, in ? r + 1 : 0, x), ms = ld(sp, in ? r - 1 : 0, x);
       vec dg;
-      if constexpr (LAP9) dg = diag(sp, mn, ms, in ? r : 1, x, i);
+      if constexpr (LAP9) dg = diag(sp, mn, ms, in ? r : 1, x);
       if (in) {
         const vec hc = ld(sq, r, x);  // h at this vector, overwritten below
         vec out;
