@@ -29,16 +29,23 @@ def hlb():
 @pytest.mark.parametrize("name,steps,stencil", [
     ("d2q9_spinodal_1024", 20, None),
     ("d2q9_spinodal_1024", 20, "standard"),
+    ("d2q9_spinodal_1024_paper", 20, None),
+    ("d2q9_spinodal_1024_paper", 20, "d2q5"),
     ("d2q9_spinodal_4096", 4, None),
     ("d3q19_spinodal_256", 2, None),
     ("d3q19_spinodal_256_iso", 2, None),
 ])
 def test_benchmark_workload_full_size(hlb, name, steps, stencil):
+    """Every benchmark workload and the timed variants that change the
+    kernels (the standard force stencil; the D2Q5 convection-diffusion model
+    at the paper's parameters, the bench's `d2q5_model` variant)."""
     import bench
 
     shape, storage, kw, desc = bench.WORKLOADS[name]
     if stencil == "standard":
         kw = dict(kw, **bench.STANDARD_STENCIL)
+    if stencil == "d2q5":
+        kw = dict(kw, cd_model=1)
     phi0 = bench.make_inputs(name, shape)
     sim = hlb.Sim(shape, storage, **kw)
     sim.init(phi0)
