@@ -232,7 +232,8 @@ void pack_all(sur_net *n) {
 
 // out = conv(in) of layer l at its level: forward (bias, ReLU) or input
 // gradient (transposed weights, optional mask).
-void conv(sur_net *n, int l, int batch, View in, View out, bool transpose, View mask) {
+void conv(sur_net *n, int l, int batch, View in, View out, bool transpose, View mask,
+          const sur::ConvFuse &fu = sur::ConvFuse{}) {
   const LayerSpec &s = n->spec[l];
   const Layout &L = n->lay;
   const int H = level_h(n->cfg, s.level), W = level_w(n->cfg, s.level);
@@ -250,7 +251,7 @@ void conv(sur_net *n, int l, int batch, View in, View out, bool transpose, View 
   const dim3 grid((unsigned)ptiles, cdiv(nct, ncg));
 #define SUR_CONV(TAPS, NCT)                                                                                        \
   hipLaunchKernelGGL((sur::k_conv<TAPS, NCT>), grid, dim3(256), 0, n->stream, H, W, in, K, frag, nkc, nct, bias, \
-                     out, N, relu, mask)
+                     out, N, relu, mask, fu)
   if (s.taps == 9) {
     if (ncg == 4) SUR_CONV(9, 4);
     else if (ncg == 2) SUR_CONV(9, 2);
@@ -295,41 +296,74 @@ long long npix_at(sur_net *n, int batch, int level) {
   return (long long)batch * level_h(n->cfg, level) * level_w(n->cfg, level);
 }
 
-void pool(sur_net *n, int batch, int level, View in, View out, int C) {
-  const int H = level_h(n->cfg, level), W = level_w(n->cfg, level);
-  hipLaunchKernelGGL(sur::k_pool, dim3(grid_for(npix_at(n, batch, level + 1) * C)), dim3(256), 0, n->stream, batch, H,
-                     W, in, out, C);
-}
-
 void up(sur_net *n, int batch, int level, View in, View out, int C) {  // level of the output
   const int H = level_h(n->cfg, level), W = level_w(n->cfg, level);
   hipLaunchKernelGGL(sur::k_up, dim3(grid_for(npix_at(n, batch, level) * C)), dim3(256), 0, n->stream, batch, H, W,
                      in, out, C);
 }
 
-void forward_normalised(sur_net *n, int batch, hipEvent_t *ev, double *conv_ms) {
-  const int c0 = n->cfg.c0, c1 = n->cfg.c1, c2 = n->cfg.c2;
+// The forward pass.  Training (x == nullptr): from the normalised input XN
+// to YN = XN + head, keeping every activation the backward pass reads.
+// Inference (x, y device arrays of the caller): y = x + scale * head(x /
+// scale), with the normalisation, the upsampling and the residual folded into
+// the convolutions (ConvFuse) instead of separate launches; the results are
+// the same floats.  Both fold the pooling into the encoder convolutions.
+void forward_normalised(sur_net *n, int batch, hipEvent_t *ev, const float *x = nullptr, float *y = nullptr) {
+  const int c1 = n->cfg.c1, c2 = n->cfg.c2;
+  const bool fused = x != nullptr;
+  const double *sc = n->cfg.scale;
   // events around each convolution when timing (ev: 2 per layer)
-  auto cv = [&](int l, View in, View out) {
+  auto cv = [&](int l, View in, View out, const sur::ConvFuse &fu = sur::ConvFuse{}) {
     if (ev) (void)hipEventRecord(ev[2 * l], n->stream);
-    conv(n, l, batch, in, out, false, kNoView);
+    conv(n, l, batch, in, out, false, kNoView, fu);
     if (ev) (void)hipEventRecord(ev[2 * l + 1], n->stream);
   };
-  (void)conv_ms;
-  cv(E0A, view(n, XN), view(n, A_E0A));
-  cv(E0B, view(n, A_E0A), view(n, U0, c1));
-  pool(n, batch, 0, view(n, U0, c1), view(n, P0), c0);
+  auto pooled = [&](Buf b) {
+    sur::ConvFuse fu{};
+    fu.pool = view(n, b);
+    return fu;
+  };
+  // upsampling folded into the decoder's first convolution, when the
+  // upsampled channels end on a 4-channel group
+  auto up_into = [&](int level, Buf src, int C, Buf dst) {
+    sur::ConvFuse fu{};
+    if (fused && C % 4 == 0) {
+      fu.up = at<float>(n, n->lay.buf[src]);
+      fu.up_C = C;
+      fu.up_off = 0;
+      fu.up_split = C;
+    } else {
+      up(n, batch, level, view(n, src), view(n, dst, 0), C);
+    }
+    return fu;
+  };
+  if (fused) {
+    sur::ConvFuse fu{};
+    fu.scale_in = 1;
+    for (int c = 0; c < 3; c++) fu.in_scale[c] = (float)(1.0 / sc[c]);
+    cv(E0A, View{const_cast<float *>(x), 3, 0}, view(n, A_E0A), fu);
+  } else {
+    cv(E0A, view(n, XN), view(n, A_E0A));
+  }
+  cv(E0B, view(n, A_E0A), view(n, U0, c1), pooled(P0));
   cv(E1A, view(n, P0), view(n, A_E1A));
-  cv(E1B, view(n, A_E1A), view(n, U1, c2));
-  pool(n, batch, 1, view(n, U1, c2), view(n, P1), c1);
+  cv(E1B, view(n, A_E1A), view(n, U1, c2), pooled(P1));
   cv(B2A, view(n, P1), view(n, A_B2A));
   cv(B2B, view(n, A_B2A), view(n, A_B2B));
-  up(n, batch, 1, view(n, A_B2B), view(n, U1, 0), c2);
-  cv(D1A, view(n, U1), view(n, A_D1A));
+  cv(D1A, view(n, U1), view(n, A_D1A), up_into(1, A_B2B, c2, U1));
   cv(D1B, view(n, A_D1A), view(n, A_D1B));
-  up(n, batch, 0, view(n, A_D1B), view(n, U0, 0), c1);
-  cv(D0A, view(n, U0), view(n, A_D0A));
+  cv(D0A, view(n, U0), view(n, A_D0A), up_into(0, A_D1B, c1, U0));
   cv(D0B, view(n, A_D0A), view(n, A_D0B));
+  if (fused) {
+    sur::ConvFuse fu{};
+    fu.resid = x;
+    for (int c = 0; c < 3; c++) {
+      fu.in_scale[c] = (float)(1.0 / sc[c]);
+      fu.out_scale[c] = (float)sc[c];
+    }
+    cv(HEAD, view(n, A_D0B), View{y, 3, 0}, fu);
+    return;
+  }
   cv(HEAD, view(n, A_D0B), view(n, HD));
   const long long ne = npix_at(n, batch, 0) * 3;
   hipLaunchKernelGGL(sur::k_add, dim3(grid_for(ne)), dim3(256), 0, n->stream, ne, at<float>(n, n->lay.buf[XN]),
@@ -514,12 +548,7 @@ hlb_status sur_forward(sur_net *n, const float *x, float *y, int batch) {
   if (!n || !x || !y) return HLB_EINVAL;
   hlb_status s = batch_ok(n, batch);
   if (s != HLB_OK) return s;
-  normalise_in(n, x, XN, batch);
-  forward_normalised(n, batch, nullptr, nullptr);
-  const long long np = npix_at(n, batch, 0);
-  const double *sc = n->cfg.scale;
-  hipLaunchKernelGGL(sur::k_scale3, dim3(grid_for(np * 3)), dim3(256), 0, n->stream, np,
-                     at<float>(n, n->lay.buf[YN]), y, (float)sc[0], (float)sc[1], (float)sc[2]);
+  forward_normalised(n, batch, nullptr, x, y);
   return scheck(n, "forward kernels");
 }
 
@@ -530,7 +559,7 @@ hlb_status sur_loss_grad(sur_net *n, const float *x, const float *target, int ba
   if (s != HLB_OK) return s;
   normalise_in(n, x, XN, batch);
   normalise_in(n, target, TN, batch);
-  forward_normalised(n, batch, nullptr, nullptr);
+  forward_normalised(n, batch, nullptr);
   const long long ne = npix_at(n, batch, 0) * 3;
   double *lp = at<double>(n, n->lay.lpart);
   hipLaunchKernelGGL(sur::k_mse, dim3(n->lay.nblk_loss), dim3(256), 0, n->stream, ne, at<float>(n, n->lay.buf[YN]),
@@ -587,12 +616,7 @@ hlb_status sur_forward_timed(sur_net *n, const float *x, float *y, int batch, in
   ms[0] = ms[1] = 0;
   for (int r = 0; r < reps && s == HLB_OK; r++) {
     (void)hipEventRecord(ev[2 * NLAYER], n->stream);
-    normalise_in(n, x, XN, batch);
-    forward_normalised(n, batch, ev.data(), nullptr);
-    const long long np = npix_at(n, batch, 0);
-    const double *sc = n->cfg.scale;
-    hipLaunchKernelGGL(sur::k_scale3, dim3(grid_for(np * 3)), dim3(256), 0, n->stream, np,
-                       at<float>(n, n->lay.buf[YN]), y, (float)sc[0], (float)sc[1], (float)sc[2]);
+    forward_normalised(n, batch, ev.data(), x, y);
     (void)hipEventRecord(ev[2 * NLAYER + 1], n->stream);
     s = scheck(n, "forward kernels");
     if (s == HLB_OK) s = ssync(n);

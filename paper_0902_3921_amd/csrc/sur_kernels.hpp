@@ -24,6 +24,29 @@ struct View {
   int C, off;
 };
 
+// Work folded into a convolution launch on the inference path, in place of
+// separate elementwise launches (all off when zero-initialised):
+//  * up: input channels [0, up_split) come from this half-resolution NHWC
+//    activation (up_C channels per pixel, from channel up_off), repeated over
+//    2 x 2 pixels (the nearest-neighbour upsampling of the decoder);
+//  * scale_in: input channel k < 3 is multiplied by in_scale[k] (the
+//    normalisation of the state);
+//  * pool: the 2 x 2 mean of the output (after bias and ReLU) is written at
+//    half resolution as well (the encoder's pooling), summed in the order
+//    of the separate pooling kernel;
+//  * resid: out = (resid * in_scale[n] + v) * out_scale[n] with resid of N
+//    channels per pixel: the residual output x + head in normalised units,
+//    scaled back, with the roundings of the separate kernels.
+struct ConvFuse {
+  const float *up;
+  int up_C, up_off, up_split;
+  int scale_in;
+  float in_scale[3];
+  View pool;
+  const float *resid;
+  float out_scale[3];
+};
+
 __device__ __forceinline__ int wrapi(int v, int n) {
   v %= n;
   return v < 0 ? v + n : v;
@@ -65,7 +88,7 @@ __global__ void __launch_bounds__(NT) k_pack(const float *__restrict__ w, int ta
 template <int TAPS, int NCT>
 __global__ void __launch_bounds__(NT) k_conv(int H, int W, View in, int K, const bf16x8 *__restrict__ frag, int nkc,
                                              int nct_total, const float *__restrict__ bias, View out, int N, int relu,
-                                             View mask) {
+                                             View mask, ConvFuse fu) {
   constexpr int TX = 16, TY = 8;
   constexpr int HALO = TAPS == 9 ? 1 : 0;
   constexpr int SX = TX + 2 * HALO, SY = TY + 2 * HALO;
@@ -89,10 +112,15 @@ __global__ void __launch_bounds__(NT) k_conv(int H, int W, View in, int K, const
       const int q = i % 8, pix = i / 8;  // 4 channels q*4 .. q*4+3 of pixel pix
       const int sx = pix % SX, sy = pix / SX;
       const int gx = wrapi(x0 + sx - HALO, W), gy = wrapi(y0 + sy - HALO, H);
-      const float *src = in.p + ((size_t)(bimg * H + gy) * W + gx) * in.C + in.off;
       const int k = 32 * kc + 4 * q;
+      // the channels of this group come from the input or, below up_split,
+      // from the half-resolution activation (up_split is a multiple of 4)
+      const bool from_up = fu.up && k < fu.up_split;
+      const float *src = from_up ? fu.up + ((size_t)(bimg * (H / 2) + gy / 2) * (W / 2) + gx / 2) * fu.up_C + fu.up_off
+                                 : in.p + ((size_t)(bimg * H + gy) * W + gx) * in.C + in.off;
+      const int sC = from_up ? fu.up_C : in.C, soff = from_up ? fu.up_off : in.off;
       float v[4];
-      if (k + 3 < K && ((in.C | in.off) & 3) == 0) {
+      if (k + 3 < K && ((sC | soff) & 3) == 0) {
         const float4 f = *reinterpret_cast<const float4 *>(src + k);
         v[0] = f.x;
         v[1] = f.y;
@@ -101,6 +129,11 @@ __global__ void __launch_bounds__(NT) k_conv(int H, int W, View in, int K, const
       } else {
 #pragma unroll
         for (int e = 0; e < 4; e++) v[e] = k + e < K ? src[k + e] : 0.f;
+      }
+      if (fu.scale_in) {
+#pragma unroll
+        for (int e = 0; e < 4; e++)
+          if (k + e < 3) v[e] *= fu.in_scale[k + e];
       }
       __bf16 *d = tile + pix * PITCH + 4 * q;
 #pragma unroll
@@ -129,7 +162,8 @@ __global__ void __launch_bounds__(NT) k_conv(int H, int W, View in, int K, const
     }
     __syncthreads();
   }
-  // epilogue: lane holds pixels 4 (lane / 16) + i of each pixel tile, channel lane % 16
+  // epilogue: lane holds pixels 4 (lane / 16) + i of each pixel tile, channel
+  // lane % 16; pixel tile pt of wave w is image row y0 + 2 w + pt
 #pragma unroll
   for (int pt = 0; pt < 2; pt++)
 #pragma unroll
@@ -146,9 +180,33 @@ __global__ void __launch_bounds__(NT) k_conv(int H, int W, View in, int K, const
         if (bias) v += bias[n];
         if (relu) v = fmaxf(v, 0.f);
         if (mask.p && !(mask.p[pix * mask.C + mask.off + n] > 0.f)) v = 0.f;
+        acc[pt][c][i] = v;  // kept for the pooled output
+        if (fu.resid) {
+#pragma clang fp contract(off)  // each product and sum rounded on its own, as in separate kernels
+          const float xn = fu.resid[pix * N + n] * fu.in_scale[n];
+          v = (xn + v) * fu.out_scale[n];
+        }
         out.p[pix * out.C + out.off + n] = v;
       }
     }
+  if (fu.pool.p) {
+    // the 2 x 2 block of pixels (x, x + 1) x (rows 2 w, 2 w + 1 of the tile)
+    // is in this lane: pixels i, i + 1 of both pixel tiles.  H and W are even
+    // and x0, y0 too, so a block lies wholly inside or wholly outside.
+#pragma unroll
+    for (int i = 0; i < 4; i += 2) {
+      const int gx = x0 + 4 * (lane / 16) + i, gy = y0 + 2 * wave;
+      if (gx >= W || gy >= H) continue;
+      const size_t po = (size_t)(bimg * (H / 2) + gy / 2) * (W / 2) + gx / 2;
+#pragma unroll
+      for (int c = 0; c < NCT; c++) {
+        const int n = 16 * (ct0 + c) + lane % 16;
+        if (ct0 + c >= nct_total || n >= N) continue;
+        const float s = (acc[0][c][i] + acc[0][c][i + 1]) + (acc[1][c][i] + acc[1][c][i + 1]);
+        fu.pool.p[po * fu.pool.C + fu.pool.off + n] = 0.25f * s;
+      }
+    }
+  }
 }
 
 // --------------------------------------------------------- weight gradient
@@ -268,20 +326,6 @@ __global__ void __launch_bounds__(NT) k_bgrad_reduce(const float *__restrict__ p
 // ------------------------------------------------------------- elementwise
 // The elementwise kernels below index with 32-bit integers: every tensor of
 // the network holds fewer than 2^31 elements (the host checks it).
-
-// 2x2 mean: out (H/2 x W/2) from in (H x W).
-__global__ void __launch_bounds__(NT) k_pool(int B, int H, int W, View in, View out, int C) {
-  const int Ho = H / 2, Wo = W / 2;
-  const int total = B * Ho * Wo * C;
-  for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
-    const int c = i % C, pix = i / C;
-    const int x = pix % Wo, y = (pix / Wo) % Ho, b = pix / (Wo * Ho);
-    const float *r0 = in.p + ((b * H + 2 * y) * W + 2 * x) * in.C + in.off + c;
-    const float *r1 = r0 + W * in.C;
-    const float s = (r0[0] + r0[in.C]) + (r1[0] + r1[in.C]);
-    out.p[pix * out.C + out.off + c] = 0.25f * s;
-  }
-}
 
 // Adjoint of the 2x2 mean: din[y][x] (+)= dout[y/2][x/2] / 4 (H, W of din).
 __global__ void __launch_bounds__(NT) k_pool_back(int B, int H, int W, View dout, View din, int C, int accumulate) {
