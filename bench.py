@@ -220,6 +220,16 @@ def run_gpu(name, steps, warmup, plan=None, profile_mode=False, variants=True):
         for vname, vkw in var_params.items():
             vsim, vsecs, _ = timed(vkw)
             var_out[vname] = {"mlups": ns * steps / vsecs / 1e6, "m": vsim.m, "substep_plan": list(vsim.plan)}
+            if vname == "d2q5_model":
+                # its two kernels: f and h collide-and-stream (18 + 10 population moves and the
+                # phi tile read, s bytes each), then phi = sum h (5 reads, 1 write)
+                us5, usphi, _, _ = vsim.time_kernels(max(20, min(200, steps // 10)))
+                b5, bphi = (18 + 10 + 1) * es, 6 * es
+                var_out[vname]["kernels"] = {
+                    "lb5": {"name": vsim.kernel_name(0), "us_per_launch": us5, "bytes_per_lu": b5,
+                            "gbs": b5 * ns / (us5 * 1e-6) / 1e9},
+                    "phi5": {"name": vsim.kernel_name(1), "us_per_launch": usphi, "bytes_per_lu": bphi,
+                             "gbs": bphi * ns / (usphi * 1e-6) / 1e9}}
             vsim.close()
 
     lb_b, ch_b, step_b = algorithmic_bytes(d, q, es)
