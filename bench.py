@@ -372,7 +372,7 @@ def run_surrogate(args):
         secs = time.perf_counter() - t0
         cpu = {"value": n / secs, "unit": "jumps/s", "cores": torch.get_num_threads(), "kind": "oracle",
                "sample": f"{n} FP64 oracle forwards of one 256x256 state (one jump each)"}
-    # the checked rollout runs the solver as the judge of every segment, so
+    # the checked rollout runs the solver over every segment to check it, so
     # its wall clock is the solver's plus the surrogate's; the speedup at the
     # tolerance exists only over segments that passed it
     checked = r["solver_s"] / r["checked_rollout_s"]

@@ -4,7 +4,7 @@
  * periodic D2Q9 simulation (phi, rho u_x, rho u_y) to the state 50
  * timesteps later (the method of arXiv:0902.3921, Sec. 2, advanced 50 times).
  * The network is trained on trajectories of that method computed by the
- * library's own solver, and the solver remains the judge of its error.
+ * library's own solver, and the solver remains the reference for its error.
  *
  * Network.  A U-Net of periodic 3x3 convolutions, each followed by a bias
  * and ReLU, with channel widths c0, c1, c2 at full, half and quarter

@@ -13,7 +13,7 @@ writes the trained FP32 parameters with the recipe that produced them.
 A rollout advances a state by jumps of the surrogate and compares phi with
 the solver every `check_every` jumps; where the relative L2 error exceeds
 the tolerance, the solver's state replaces the surrogate's (a fallback).
-The solver runs every segment as the judge, so a checked rollout costs the
+The solver runs every segment to check it, so a checked rollout costs the
 solver's time plus the surrogate's; its times are reported separately.
 """
 from __future__ import annotations
@@ -136,10 +136,10 @@ def rollout(net, seed: int, jumps: int = 100, check_every: int = 10, tol: float 
     """Surrogate rollout from the solver's state at t0 of trajectory `seed`,
     checked against the solver every check_every jumps; where phi's relative
     L2 error exceeds `tol` the solver's state replaces the surrogate's (a
-    fallback).  The solver runs every segment, as the judge.  Returns a dict
+    fallback).  The solver runs every segment to check it.  Returns a dict
     with the times of the solver's segments (all, and those whose surrogate
     segment passed), of the surrogate's forwards (all, and those that
-    passed), the wall clock of the checked rollout (surrogate plus judge),
+    passed), the wall clock of the checked rollout (surrogate plus checking solver),
     the errors at every check and the number of fallbacks."""
     import torch
 

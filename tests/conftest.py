@@ -15,8 +15,8 @@ def pytest_configure(config):
 
 @pytest.fixture(autouse=True)
 def _announce_gpu_case(request):
-    """Print the case name before each GPU test, so a run that ends the box
-    still names what it was doing."""
+    """Print the case name before each GPU test, so a run that stops on a
+    device fault still names the case it was running."""
     if request.node.get_closest_marker("gpu") is not None:
         print(f"\n[gpu case] {request.node.nodeid}", flush=True)
     yield

@@ -183,7 +183,7 @@ def test_rollout_checks_and_falls_back(sur):
     r = st.rollout(net, seed=7, jumps=4, check_every=2, tol=1e-2, t0=200)
     assert r["fallbacks"] == 2 and all(e > 1e-2 for e in r["errors"])
     assert r["accepted"] == 0 and r["solver_accepted_s"] == 0.0 and r["surrogate_accepted_s"] == 0.0
-    # the judge runs every segment: the checked rollout costs the solver plus the surrogate
+    # the solver runs every segment: the checked rollout costs the solver plus the surrogate
     assert r["checked_rollout_s"] == r["solver_s"] + r["surrogate_s"]
     r2 = st.rollout(net, seed=7, jumps=4, check_every=2, tol=float("inf"), t0=200)
     assert r2["fallbacks"] == 0 and r2["accepted"] == 2
