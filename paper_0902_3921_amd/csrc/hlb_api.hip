@@ -1508,9 +1508,11 @@ hlb_status hlb_autotune(hlb_ctx *c, double *best_us) {
   // substeps then read), so repeating it leaves the state as it was.  The
   // substeps run from the current phi into two scratch buffers in the staging
   // area.  The collide-and-stream launch alone is timed first and subtracted.
+  // The minimum over 8 runs after a warm-up: candidates within a few per cent
+  // of each other swapped places between runs with 3.
   auto timed = [&](bool with_substeps, float &tmin) {
     tmin = 1e30f;
-    for (int rep = 0; rep < 4; rep++) {
+    for (int rep = 0; rep < 9; rep++) {
       (void)hipEventRecord(e0, c->stream);
       dispatch(c, [&](auto ops) {
         using T = typename decltype(ops)::Type;
